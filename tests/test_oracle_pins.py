@@ -1,0 +1,314 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test names the passage it pins.  None of them re-types the oracle's
+formulas: they check exact counts printed in the paper, brute-force
+enumerations, algebraic identities the discrete system must satisfy, closed-form
+special cases, and paper-printed values.
+"""
+import itertools
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from conftest import golden
+from knp_inputs import config_case, model_a_case
+from oracle import timeloop
+from oracle.assemble import (Assembler, bulk_coo, gamma_coo, gamma_values, hh_rates,
+                             initial_gates, initial_state, rush_larsen, p0_values)
+from oracle.mesh import build_layout, structural_pattern
+from oracle.solve import dense_solve, gmres, lu_solve
+
+
+def dof_formula(nx, d, p=1, K=3):
+    """N = ((p N_x + 1)^d + (3 - d/2)(p N_x)^(d-1) + 2(d - 2)) (|K| + 1), Sec. "Model A"."""
+    return int(round(((p * nx + 1) ** d + (3 - d / 2) * (p * nx) ** (d - 1) + 2 * (d - 2)) * (K + 1)))
+
+
+# --------------------------------------------------------------------------- counts
+@pytest.mark.parametrize("row", golden("table2_dofs.txt"))
+def test_table2_dof_counts(row):
+    nx, N = int(row[0]), int(row[1])
+    assert dof_formula(nx, 2) == N
+    lay = build_layout(model_a_case(2, nx))
+    assert lay.N == N
+
+
+@pytest.mark.parametrize("d,nx", [(2, 4), (2, 8), (3, 4), (3, 8), (3, 12)])
+def test_dof_formula_small(d, nx):
+    lay = build_layout(model_a_case(d, nx))
+    assert lay.N == dof_formula(nx, d)
+    # duplicated membrane vertices: N_i + N_e - n_vert = |Gamma vertices|
+    assert sum(lay.N_r) - lay.n_vert == len(lay.gamma)
+
+
+def _brute_pattern(case):
+    """Structural pattern by plain set enumeration over elements and facets."""
+    lay = build_layout(case)
+    Ni, Ne = lay.N_r
+    off = (0, 4 * Ni)
+    Nr = (Ni, Ne)
+    pairs = [set(), set()]
+    for e, t in zip(case.elem.tolist(), case.tag.tolist()):
+        r = 0 if t >= 1 else 1
+        for a in e:
+            for b in e:
+                pairs[r].add((a, b))
+    gam = set()
+    for f in lay.facets.tolist():
+        for a in f:
+            for b in f:
+                gam.add((a, b))
+    ent = set()
+    loc = lay.loc
+    for r in (0, 1):
+        q = 1 - r
+        for (a, b) in pairs[r]:
+            ja, jb = loc[r, a], loc[r, b]
+            for k in range(3):
+                ent.add((off[r] + k * Nr[r] + ja, off[r] + k * Nr[r] + jb))
+                ent.add((off[r] + k * Nr[r] + ja, off[r] + 3 * Nr[r] + jb))
+                ent.add((off[r] + 3 * Nr[r] + ja, off[r] + k * Nr[r] + jb))
+            ent.add((off[r] + 3 * Nr[r] + ja, off[r] + 3 * Nr[r] + jb))
+        for (a, b) in gam:
+            ja, jb = loc[r, a], loc[q, b]
+            for f in range(4):
+                ent.add((off[r] + f * Nr[r] + ja, off[q] + 3 * Nr[q] + jb))
+    return lay, pairs, gam, ent
+
+
+@pytest.mark.parametrize("d,nx,N,nnz", [(2, 4, 132, 1802), (3, 4, 604, 16390)])
+def test_pattern_bruteforce_tiny(d, nx, N, nnz):
+    case = model_a_case(d, nx)
+    lay, pairs, gam, ent = _brute_pattern(case)
+    rowptr, colidx = structural_pattern(case, lay)
+    assert lay.N == N
+    assert len(colidx) == nnz == len(ent)
+    # closed form nnz = 10 sum_r P_r + 8 P_Gamma for three ions
+    assert nnz == 10 * (len(pairs[0]) + len(pairs[1])) + 8 * len(gam)
+    rows = np.repeat(np.arange(lay.N), np.diff(rowptr))
+    got = set(zip(rows.tolist(), colidx.tolist()))
+    assert got == ent
+    # columns strictly ascending within each row
+    for i in range(lay.N):
+        seg = colidx[rowptr[i]:rowptr[i + 1]]
+        assert np.all(np.diff(seg) > 0)
+
+
+def test_pattern_config1_and_interior_row_lengths():
+    case = config_case(1)
+    asm = Assembler(case)
+    assert asm.lay.N == 4612 and len(asm.colidx) == 77066
+    lens = np.diff(asm.rowptr)
+    # 2D right-diagonal split: 6 neighbours + self -> c-rows 14, phi-rows 28 in the interior
+    assert np.bincount(lens).argmax() in (14,)
+    assert 28 in set(lens.tolist())
+    case3 = model_a_case(3, 8)
+    asm3 = Assembler(case3)
+    lens3 = np.diff(asm3.rowptr)
+    # 3D Kuhn split: 14 neighbours + self -> c-rows 30, phi-rows 60 in the interior
+    assert lens3.max() >= 60 and 30 in set(lens3.tolist()) and 60 in set(lens3.tolist())
+
+
+# --------------------------------------------------------------------------- algebra
+@pytest.fixture(scope="module")
+def run2d():
+    case = config_case(1)
+    return case, timeloop.run(case, n_steps=2, keep_systems=True)
+
+
+@pytest.fixture(scope="module")
+def run3d():
+    case = model_a_case(3, 8, "hh", 5e-5, 2, cfg_id=2)
+    return case, timeloop.run(case, n_steps=2, keep_systems=True)
+
+
+@pytest.mark.parametrize("which", ["run2d", "run3d"])
+def test_nullspace_unpinned(which, request):
+    """The unpinned operator annihilates e = (0, 1_i, 0, 1_e) from both sides and the
+    potential rows of f sum to zero (Remark on the constant-potential nullspace)."""
+    case, res = request.getfixturevalue(which)
+    asm = res["asm"]
+    lay = asm.lay
+    Ni, Ne = lay.N_r
+    s = asm.assemble(res["u"][1], res["gates"][1], 2 * case.dt, case.dt, pin=False)
+    A = s.csr()
+    e = np.zeros(lay.N)
+    e[3 * Ni:4 * Ni] = 1.0
+    e[4 * Ni + 3 * Ne:] = 1.0
+    absA = abs(A)
+    assert np.abs(A @ e).max() <= 1e-13 * (absA @ e).max()
+    assert np.abs(A.T @ e).max() <= 1e-13 * (absA.T @ e).max()
+    assert abs(e @ s.f) <= 1e-13 * np.abs(s.f * e).sum()
+
+
+def _mass(case, lay, r):
+    rr, cc, vv = bulk_coo(case, lay, r, kind="mass")
+    return sp.coo_matrix((vv, (rr, cc)), shape=(lay.N_r[r],) * 2).tocsr()
+
+
+def _gmass(case, lay, weight=None):
+    gr, gc, gv = gamma_coo(case, lay, weight)
+    return sp.coo_matrix((gv, (gr, gc)), shape=(lay.n_vert,) * 2).tocsr()
+
+
+@pytest.mark.parametrize("which", ["run2d", "run3d"])
+def test_invariants(which, request):
+    """I1: sum_k z_k c_k is unchanged at every node (electroneutrality, eq. ``knp``).
+    I2: per cell, C_m int (phi_M^n - phi_M^{n-1}) = -dt int I_ch (test w = 1 on the
+        cell in eq. ``weak_disc2``).
+    I3: per ion and region, int (c^n - c^{n-1}) = -sgn_r/(F z_k) [dt int I^k +
+        C_m int alpha_r^k (phi_M^n - phi_M^{n-1})] (test v = 1 in eq. ``weak_disc``).
+    """
+    case, res = request.getfixturevalue(which)
+    asm = res["asm"]
+    lay = asm.lay
+    p = case.params
+    z = np.array(p["z"])
+    F, Cm = p["F"], p["C_m"]
+    u0, u1 = res["u"][0], res["u"][1]
+    mem = res["systems"][0].mem
+    for r in (0, 1):
+        idx = np.arange(lay.N_r[r])
+        q0 = sum(z[k] * u0[lay.dof(r, k, idx)] for k in range(3))
+        q1 = sum(z[k] * u1[lay.dof(r, k, idx)] for k in range(3))
+        # round-off floor: the pinned node's potential equation is only implied by
+        # the others, so its charge balance carries their accumulated rounding
+        assert np.abs(q1 - q0).max() <= 1e-9 * 137.0
+
+    def on_gamma(x):
+        y = np.zeros(lay.n_vert)
+        y[lay.gamma] = x
+        return y
+
+    MG = _gmass(case, lay)
+    _, _, ph0 = gamma_values(lay, u0)
+    _, _, ph1 = gamma_values(lay, u1)
+    dph = on_gamma(ph1 - ph0)
+    ones_cell = on_gamma(np.ones(len(lay.gamma)))
+    lhs = Cm * ones_cell @ (MG @ dph)
+    rhs = -case.dt * ones_cell @ (MG @ on_gamma(mem.I.sum(axis=1)))
+    assert abs(lhs - rhs) <= 1e-6 * abs(rhs)
+
+    for r in (0, 1):
+        sgn = 1.0 if r == 0 else -1.0
+        M = _mass(case, lay, r)
+        idx = np.arange(lay.N_r[r])
+        for k in range(3):
+            c0 = u0[lay.dof(r, k, idx)]
+            dc = u1[lay.dof(r, k, idx)] - c0
+            content = abs(M.sum(axis=0).A1 @ c0)
+            lhs = M.sum(axis=0).A1 @ dc
+            MGa = _gmass(case, lay, on_gamma(mem.alpha[r, :, k]))
+            rhs = -sgn / (F * z[k]) * (case.dt * np.ones(lay.n_vert) @ (MG @ on_gamma(mem.I[:, k]))
+                                        + Cm * np.ones(lay.n_vert) @ (MGa @ dph))
+            assert abs(lhs - rhs) <= 1e-11 * content
+            assert abs(rhs) > 1e-6 * abs(lhs - rhs) + 0.0
+
+
+# --------------------------------------------------------------------------- membrane
+def test_hh_steady_state_matches_table():
+    p = config_case(1).params
+    alpha, beta = hh_rates(np.array([p["phi_M0"]]), p["phi_rest"])
+    w_inf = (alpha / (alpha + beta))[0]
+    printed = {r[0]: float(r[1]) for r in golden("hh_initial_gates.txt")}
+    for i, name in enumerate("nmh"):
+        assert abs(w_inf[i] - printed[name]) < 1.5e-3, (name, w_inf[i], printed[name])
+
+
+def test_hh_rates_removable_points():
+    """alpha_n at V = 10 mV and alpha_m at V = 25 mV equal their limits 0.1 and 1 /ms."""
+    rest = -0.065
+    a, _ = hh_rates(np.array([rest + 0.010, rest + 0.025]), rest)
+    assert abs(a[0, 0] - 100.0) < 1e-12 and abs(a[1, 1] - 1000.0) < 1e-12
+    eps = 1e-9
+    a2, _ = hh_rates(np.array([rest + 0.010 + eps, rest + 0.025 + eps]), rest)
+    assert abs(a2[0, 0] - 100.0) < 1e-4 and abs(a2[1, 1] - 1000.0) < 1e-3
+
+
+def test_rush_larsen_composes_exactly():
+    """With phi_M frozen the gating ODE is linear with constant coefficients, so n
+    Rush-Larsen sub-steps equal the exact solution over dt."""
+    rng = np.random.default_rng(0)
+    phi = rng.uniform(-0.09, 0.04, size=64)
+    w0 = rng.uniform(0, 1, size=(64, 3))
+    dt = 5e-5
+    got = rush_larsen(w0, phi, -0.065, dt, 25)
+    a, b = hh_rates(phi, -0.065)
+    winf = a / (a + b)
+    exact = winf + (w0 - winf) * np.exp(-(a + b) * dt)
+    assert np.abs(got - exact).max() < 1e-14
+
+
+def test_no_channels_uniform_state_is_stationary():
+    """All conductances zero and uniform electroneutral data: u_n = u_0 exactly."""
+    case = model_a_case(2, 16, "leak", 1e-4, 3)
+    case.params["g_leak"] = [0.0, 0.0, 0.0]
+    for r, base in enumerate((case.params["conc_i0"], case.params["conc_e0"])):
+        for k in range(3):
+            case.conc0[r, k] = base[k]
+    res = timeloop.run(case)
+    for u in res["u"][1:]:
+        # sparse-LU rounding floor of this system (cond > 1e10) is ~1e-11 relative
+        assert np.abs(u - res["u"][0]).max() <= 1e-10 * np.abs(res["u"][0]).max()
+
+
+def test_sign_of_h_is_pinned():
+    """Flipping the printed sign of h breaks the per-cell capacitive balance I2."""
+    case = config_case(1)
+    asm = Assembler(case)
+    lay = asm.lay
+    u0 = initial_state(case, lay)
+    w0 = initial_gates(case, lay)
+    s = asm.assemble(u0, w0, case.dt, case.dt)
+    # h_r must equal sum_k z_k g_r^k (what eq. weak_disc2 needs to be the sum of weak_disc)
+    z = np.array(case.params["z"])
+    for r in (0, 1):
+        assert np.allclose(s.mem.h[r], (s.mem.g[r] * z[None, :]).sum(axis=1), rtol=1e-13, atol=0)
+
+
+# --------------------------------------------------------------------------- solvers
+@pytest.mark.parametrize("d", [2, 3])
+def test_tiny_bruteforce_solves_agree(d):
+    case = model_a_case(d, 4, "hh" if d == 3 else "leak", 1e-4, 1)
+    asm = Assembler(case)
+    lay = asm.lay
+    s = asm.assemble(initial_state(case, lay), initial_gates(case, lay), case.dt, case.dt)
+    A = s.csr()
+    x_lu = lu_solve(A, s.f)
+    x_de = dense_solve(A, s.f)
+    # full GMRES on the symmetrically diagonally scaled system (same solution)
+    dsc = 1.0 / np.sqrt(A.diagonal())
+    S = sp.diags(dsc)
+    y, info = gmres(S @ A @ S, dsc * s.f, restart=None, rtol=1e-15, maxiter=lay.N)
+    x_gm = dsc * y
+    scale = np.abs(x_de).max()
+    assert np.abs(x_lu - x_de).max() <= 1e-12 * scale
+    assert np.abs(x_gm - x_de).max() <= 1e-12 * scale
+
+
+@pytest.mark.parametrize("row", golden("lu_p0_iterations.txt"))
+def test_lu_p0_gmres_iteration_count(row):
+    """GMRES preconditioned by the exact block-diagonal P_0 converges in 3-4
+    iterations on Model A 2D (Sec. "Iterative solver robustness").  The criterion
+    is the preconditioned relative residual (left preconditioning), the default
+    of the solver library the paper uses; initial guess u_0 as in Sec. "Solver
+    configurations".  Model A has uniform initial concentrations."""
+    dt, printed = float(row[0]), int(row[1])
+    case = model_a_case(2, 32, "hh", dt, 1)
+    for r, base in enumerate((case.params["conc_i0"], case.params["conc_e0"])):
+        for k in range(3):
+            case.conc0[r, k] = base[k]
+    asm = Assembler(case)
+    lay = asm.lay
+    u0 = initial_state(case, lay)
+    s = asm.assemble(u0, initial_gates(case, lay), dt, dt)
+    A = s.csr()
+    P0 = sp.csr_matrix((p0_values(s, lay), s.colidx, s.rowptr), shape=A.shape)
+    lu = spla.splu(sp.csc_matrix(P0))
+    _, info = gmres(lambda v: lu.solve(A @ v), lu.solve(s.f), x0=u0, restart=30,
+                    rtol=1e-6, maxiter=100)
+    assert 3 <= info["its"] <= 4 and (printed == 3 or info["its"] == printed), info["its"]
+    _, info0 = gmres(A, s.f, x0=u0, restart=30, rtol=1e-6, maxiter=300)
+    assert info0["its"] >= 100          # unpreconditioned GMRES stalls (same section)
