@@ -1,0 +1,213 @@
+#!/usr/bin/env python3
+"""Throughput of the KNP-EMI time-step solve on one MI355X.
+
+Workload: a 4x4x4 lattice of jittered box cells in [0,4]^3 um on a 132^3 grid
+split into 6 tetrahedra per cube (~1.0e7 unknowns), 3 ions + potential, 16
+Hodgkin-Huxley cells with stimulus and passive leak elsewhere, dt = 0.05 ms,
+seeded +-1% concentration perturbations (synthetic; see knp_inputs).
+
+One step = assemble A_{n-1}, f_n on the device + solve with right-preconditioned
+FGMRES(30) and one AMG(P_0) V-cycle per iteration at rtol 1e-6.  Runs the FP64
+hierarchy and the FP32-stored hierarchy from the same initial state; W warm-up
+steps (including the one-off AMG setup after step 1) then exactly K timed steps.
+Prints one JSON line; `value` is the FP32-AMG steps/s, the FP64 figures sit
+beside it.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+
+
+def block_errors(info, u, ref):
+    import numpy as np
+    Ni, Ne = info.N_i, info.N_e
+    out = {}
+    for k, b in {"c_i": np.r_[0:3 * Ni], "c_e": np.r_[4 * Ni:4 * Ni + 3 * Ne],
+                 "phi": np.r_[3 * Ni:4 * Ni, 4 * Ni + 3 * Ne:4 * (Ni + Ne)]}.items():
+        out[k] = float(np.linalg.norm(u[b] - ref[b]) / np.linalg.norm(ref[b]))
+    return out
+
+
+def run_precision(solver, u0, g0, precision, warmup, steps, log, first_restart):
+    import torch
+    from paper_2403_04491_amd import amg_opts, solve_opts
+    solver.u = u0.clone()
+    solver.gates = g0.clone()
+    solver.n = 0
+    solver.amg_opts = amg_opts(precision=precision)
+    solver.amg_ready = False
+    t_setup = time.perf_counter()
+    its_w = []
+    for w in range(warmup):
+        if w == 0:
+            solver.assemble()
+            torch.cuda.synchronize()
+            setup_s = time.perf_counter() - t_setup
+            # the first step absorbs the seeded per-node noise; its preconditioned
+            # spectrum needs a Krylov polynomial of high degree (long restart)
+            x, info, ok = solver.solve(opts=solve_opts(rtol=1e-6, restart=first_restart, max_it=4000))
+            solver.u = x
+            solver.n += 1
+        else:
+            info = solver.step()
+        its_w.append(info.its)
+        log(f"  warmup step {solver.n}: its={info.its} rel_res={info.rel_res:.2e}")
+    torch.cuda.synchronize()
+    solver.ctx.timing(True)
+    its = []
+    t0 = time.perf_counter()
+    for k in range(steps):
+        info = solver.step()
+        its.append(info.its)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    timers = solver.ctx.timing_read()
+    solver.ctx.timing(False)
+    log(f"  timed {steps} steps in {elapsed:.3f} s, its={its}")
+    return {"steps_per_s": steps / elapsed, "ms_per_step": 1e3 * elapsed / steps, "its": its,
+            "its_warmup": its_w, "amg_setup_s": setup_s, "timers": timers,
+            "u": solver.u.cpu().numpy()}
+
+
+def roofline_of(timers):
+    best = None
+    for name in ("spmv_A", "cheb_L0", "resid_L0"):
+        t = timers[name]
+        if t["launches"] == 0:
+            continue
+        if best is None or t["total_ms"] > timers[best]["total_ms"]:
+            best = name
+    t = timers[best]
+    per_launch_bytes = t["bytes"] / t["launches"]
+    avg_s = t["total_ms"] / t["launches"] * 1e-3
+    achieved = per_launch_bytes / avg_s / 1e9
+    return best, {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                  "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                  "kernel": best, "bytes_per_launch": per_launch_bytes,
+                  "avg_launch_us": round(avg_s * 1e6, 2), "launches": t["launches"]}
+
+
+def cpu_baseline(per_pitch, n_steps, log):
+    """The oracle (float64 assembly + SuperLU) on a reduced member of the same
+    lattice family, timed on this host."""
+    import numpy as np
+    from knp_inputs import config_case
+    from oracle.assemble import Assembler, initial_gates, initial_state
+    from oracle.timeloop import step as oracle_step
+    case = config_case(3, per_pitch=per_pitch, n_steps=n_steps)
+    asm = Assembler(case)
+    u = initial_state(case, asm.lay)
+    w = initial_gates(case, asm.lay)
+    times = []
+    for n in range(1, n_steps + 1):
+        t0 = time.perf_counter()
+        u, w, _ = oracle_step(asm, u, w, n, case.dt)
+        times.append(time.perf_counter() - t0)
+        log(f"  oracle step {n}: {times[-1]:.2f} s (N={asm.lay.N})")
+    per_step = float(np.median(times))
+    return {"value": round(1.0 / per_step, 5), "unit": "time steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n_steps} oracle steps (assembly + SuperLU) of the same 4x4x4 lattice family at "
+                      f"{case.shape[0]}^3 grid, N={asm.lay.N} unknowns (not the full ~1e7 problem, "
+                      f"which the direct solver cannot factor); median s/step {per_step:.2f}",
+            "host_cores_available": len(os.sched_getaffinity(0)),
+            "threads_env": {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS")}}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=8)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--per-pitch", type=int, default=33, help="grid intervals per cell pitch (33 = ~1e7 unknowns)")
+    ap.add_argument("--precision", choices=["both", "fp64", "fp32"], default="both")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-per-pitch", type=int, default=4)
+    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--first-restart", type=int, default=200,
+                    help="FGMRES restart of the untimed first step (later steps: 30)")
+    ap.add_argument("--quiet", action="store_true")
+    args = ap.parse_args()
+
+    def log(msg):
+        if not args.quiet:
+            print(msg, file=sys.stderr, flush=True)
+
+    if args.warmup < 1:
+        ap.error("--warmup must be >= 1 (the first step includes the AMG setup)")
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1 "
+                                   "(the multi-GPU sharding is a design, not a code path)"}))
+        sys.exit(2)
+    import torch
+    from knp_inputs import config_case
+    from paper_2403_04491_amd import KnpSolver, solve_opts
+
+    t0 = time.perf_counter()
+    case = config_case(3, per_pitch=args.per_pitch, n_steps=args.warmup + args.steps)
+    t_gen = time.perf_counter() - t0
+    log(f"case {case.name}: {case.n_vert} vertices, {case.n_elem} tets, generated in {t_gen:.1f} s")
+    t0 = time.perf_counter()
+    solver = KnpSolver(case, solve=solve_opts(rtol=1e-6, restart=30, max_it=2000))
+    torch.cuda.synchronize()
+    t_upload = time.perf_counter() - t0
+    info = solver.info
+    log(f"mesh upload {t_upload:.1f} s: N={info.N} nnz(A)={info.nnz_A} nnz(P0)={info.nnz_P0}")
+    u0 = solver.u.clone()
+    g0 = solver.gates.clone()
+    runs = {}
+    order = {"both": [0, 1], "fp64": [0], "fp32": [1]}[args.precision]
+    for prec in order:
+        name = "fp64" if prec == 0 else "fp32_amg"
+        log(f"[{name}]")
+        runs[name] = run_precision(solver, u0, g0, prec, args.warmup, args.steps, log, args.first_restart)
+    head = runs.get("fp32_amg") or runs["fp64"]
+    kernel, roof = roofline_of(head["timers"])
+    extra = {}
+    if "fp64" in runs and "fp32_amg" in runs:
+        extra["fp32_amg_vs_fp64_final_step_rel_err"] = block_errors(info, runs["fp32_amg"]["u"], runs["fp64"]["u"])
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[cpu baseline]")
+        cpu = cpu_baseline(args.cpu_per_pitch, args.cpu_steps, log)
+    out = {
+        "metric": "time steps/s at ~1e7 unknowns (FP64 vs FP32-AMG), GMRES its/step, HBM GB/s",
+        "value": round(head["steps_per_s"], 3),
+        "unit": "time steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(head["ms_per_step"], 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64 (AMG levels f32)" if "fp32_amg" in runs else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"4x4x4 lattice of jittered box cells, {case.shape[0]}^3 grid x 6 tets, "
+                               f"N={info.N} unknowns, 16 HH + 48 leak cells, dt=0.05 ms, FGMRES(30) rtol 1e-6",
+                   "N": info.N, "nnz_A": info.nnz_A, "nnz_P0": info.nnz_P0, "parallelism": "1 GPU"},
+        "its_per_step": {k: float(sum(r["its"]) / len(r["its"])) for k, r in runs.items()},
+        "steps_per_s": {k: round(r["steps_per_s"], 3) for k, r in runs.items()},
+        "ms_per_step_by_precision": {k: round(r["ms_per_step"], 2) for k, r in runs.items()},
+        "setup_s": {"mesh_upload": round(t_upload, 2),
+                    **{f"amg_setup_{k}": round(r["amg_setup_s"], 2) for k, r in runs.items()}},
+        "kernel_gbs": {k: {n: round(t["bytes"] / (t["total_ms"] * 1e-3) / 1e9, 1)
+                           for n, t in r["timers"].items() if t["launches"] and t["bytes"] > 0}
+                       for k, r in runs.items()},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        **extra,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

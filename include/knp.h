@@ -1,0 +1,226 @@
+/*
+ * knp.h -- C ABI of libknp: one time step of the KNP-EMI ionic electrodiffusion
+ * model (IMEX-linearised finite element system) assembled and solved on one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The calls follow the paper's statement of the problem: for n = 1..N_t find the
+ * ion concentrations [k]_r^n and potentials phi_r^n of the intra- (r = i) and
+ * extracellular (r = e) regions (Sec. "Time discretization"), given a conforming
+ * simplicial mesh whose cells match at the membrane Gamma (Sec. "Spatial
+ * discretization"), the physical parameters (Table "physconst"), the initial
+ * state and dt.  Each step is the linear system A_{n-1} u_n = f_n of eq.
+ * ``lin_sys``, solved by GMRES preconditioned with one algebraic-multigrid
+ * V-cycle on the frozen block-diagonal matrix P_0 of eq. ``P_prec``
+ * (Sec. "Solution and preconditioning strategy").
+ *
+ * Conventions shared by every call
+ *  - Status: every call returns knp_status; on failure knp_last_error() gives a
+ *    text.  No C++ exception crosses the ABI.  KNP_E_ARG leaves the context
+ *    unchanged.
+ *  - Host pointers ("host") are read during the call only; the caller keeps
+ *    ownership.  Device pointers ("device") are HIP device memory owned by the
+ *    caller (for example torch tensors); the library never frees them.
+ *  - All device work is enqueued on the stream given to knp_create.  Calls that
+ *    return host-visible results (solver statistics, layouts) synchronise that
+ *    stream before returning.  One context per host thread.
+ *  - Unknown vector layout (eq. ``lin_sys``): u = [c_i^Na, c_i^K, c_i^Cl, phi_i,
+ *    c_e^Na, c_e^K, c_e^Cl, phi_e], each block of length N_r, region DOFs ordered
+ *    by ascending global vertex id; membrane vertices appear once in each region.
+ *    DOF(r, f, j) = off_r + f * N_r + j with off_i = 0, off_e = 4 N_i.
+ *  - Units: SI (m, s, mol/m^3, V, S/m^2, F/m^2).
+ */
+#ifndef KNP_H
+#define KNP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct knp_ctx knp_ctx;
+
+typedef enum {
+    KNP_OK = 0,
+    KNP_E_ARG = 1,      /* invalid argument; nothing was changed                */
+    KNP_E_STATE = 2,    /* call out of order (e.g. solve before setup)          */
+    KNP_E_HIP = 3,      /* HIP runtime error                                    */
+    KNP_E_NOMEM = 4,    /* device or host allocation failed                     */
+    KNP_E_NOCONV = 5,   /* solver hit max_it; x holds the last (best) iterate   */
+    KNP_E_NUMERIC = 6   /* NaN or Inf in the data                               */
+} knp_status;
+
+/* Sizes reported by knp_mesh_upload. */
+typedef struct {
+    int64_t n_vert, n_elem;
+    int64_t N_i, N_e;       /* P1 DOFs (vertices) of the ICS and ECS             */
+    int64_t N;              /* unknowns = 4 (N_i + N_e)                          */
+    int64_t nnz_A;          /* structural nonzeros of A                          */
+    int64_t nnz_P0;         /* structural nonzeros of P_0                        */
+    int64_t n_gamma;        /* membrane vertices (one pair of DOFs each)         */
+    int64_t n_facets;       /* membrane facets                                   */
+    int32_t n_cells;        /* cells (ICS components), tags 1..n_cells           */
+    int32_t dim;
+    int64_t pin_dof;        /* the pinned phi_e DOF                              */
+} knp_mesh_info;
+
+/* Physical parameters (Table "physconst") and membrane models
+ * (eq. ``HH_ionic_model``; passive leak: every ion I_k = theta g_leak^k (phi_M - E_k)). */
+typedef struct {
+    double R, T, F, C_m;
+    double z[3];            /* valences of Na+, K+, Cl-                           */
+    double D[3];            /* diffusion coefficients, same in both regions       */
+    double g_leak[3];       /* leak conductances                                  */
+    double gbar_Na, gbar_K; /* Hodgkin-Huxley maximal conductances                */
+    double g_stim_bar;      /* stimulus g_stim(t) = g_stim_bar exp(-(t mod tau)/a)*/
+    double stim_a, stim_tau;
+    double phi_rest;        /* HH resting potential                               */
+    int32_t n_ode;          /* Rush-Larsen sub-steps per time step                */
+    int32_t n_cells;        /* must equal knp_mesh_info.n_cells                   */
+    const int32_t *cell_model;  /* host [n_cells]: 0 passive leak, 1 Hodgkin-Huxley */
+    const int32_t *cell_stim;   /* host [n_cells]: 1 = stimulus on this cell's membrane */
+} knp_params;
+
+typedef struct {
+    int32_t precision;      /* 0: levels stored and applied in FP64; 1: FP32      */
+    double strength;        /* strength-of-connection threshold (0 < s < 1)       */
+    int32_t cheb_degree;    /* Chebyshev smoother degree, pre and post (>= 1)     */
+    double cheb_ratio;      /* smoothing interval [lmax/cheb_ratio, lmax] (> 1)   */
+    int32_t coarse_max;     /* coarsen until at most this many unknowns           */
+    int32_t max_levels;
+} knp_amg_opts;
+
+typedef struct {
+    double rtol;            /* stop when ||S(b - A x)||_2 <= rtol ||S b||_2       */
+    int32_t restart;        /* Krylov subspace size per cycle (paper: 30)         */
+    int32_t max_it;         /* total iteration cap                                */
+    int32_t reorth;         /* 1: second classical Gram-Schmidt pass              */
+    int32_t precond;        /* 1: AMG V-cycle on P_0 (needs knp_amg_setup); 0: none */
+} knp_solve_opts;
+
+typedef struct {
+    int32_t its;            /* iterations performed                               */
+    int32_t restarts;
+    double rel_res;         /* recomputed ||S(b - A x)|| / ||S b|| at return      */
+    double rel_res_est;     /* the recurrence's estimate at the last iteration    */
+} knp_solve_info;
+
+/* Create a context on HIP device `hip_device`, enqueuing on `hip_stream`
+ * (a hipStream_t; NULL = the default stream).  hip_device = -1 creates a
+ * host-only context in which only knp_mesh_upload, knp_get_layout and
+ * knp_get_gamma work (for checks of the host-side mesh logic). */
+knp_status knp_create(knp_ctx **out, int hip_device, void *hip_stream);
+void knp_destroy(knp_ctx *ctx);
+const char *knp_last_error(const knp_ctx *ctx);
+
+/* Mesh and DOF setup (Sec. "Spatial discretization"; Remark ``rem:nullspace``).
+ * xyz: host [n_vert*dim] vertex coordinates (m); elem_vert: host
+ * [n_elem*(dim+1)] simplices; elem_tag: host [n_elem], 0 = extracellular,
+ * c >= 1 = cell c (cells numbered 1..n_cells, each a separate ICS component).
+ * Membrane facets are the faces shared by a cell element and an extracellular
+ * element.  pin_vertex: the extracellular vertex (off the membrane) whose phi_e
+ * is pinned to 0.  Builds the DOF maps and the structural CSR pattern of A on
+ * the host and uploads them once.  Errors (KNP_E_ARG): dim not 2 or 3, indices
+ * out of range, two cells touching, a cell touching the outer boundary, a pin
+ * on the membrane, a vertex whose degree exceeds the assembly kernel's limit.
+ * May be called once per context. */
+knp_status knp_mesh_upload(knp_ctx *ctx, int dim, int64_t n_vert, const double *xyz,
+                           int64_t n_elem, const int32_t *elem_vert,
+                           const int32_t *elem_tag, int64_t pin_vertex,
+                           knp_mesh_info *out);
+
+/* Host copies of the structural pattern and DOF maps for bit-exact checks:
+ * rowptr [N+1] (int64), colidx [nnz_A] (int32, strictly ascending per row),
+ * dof_vertex [N] (global vertex of each DOF).  Any pointer may be NULL. */
+knp_status knp_get_layout(knp_ctx *ctx, int64_t *rowptr, int32_t *colidx,
+                          int32_t *dof_vertex);
+
+/* Host copy of the membrane vertex ids, ascending [n_gamma]: the row order of
+ * the gates array of knp_assemble_step. */
+knp_status knp_get_gamma(knp_ctx *ctx, int32_t *gamma_vertex);
+
+/* Physical parameters; copies everything it needs.  Required before the first
+ * knp_assemble_step. */
+knp_status knp_set_params(knp_ctx *ctx, const knp_params *params);
+
+/* Assemble A_{n-1} and f_n (eq. ``lin_sys``; its block rows come from eqs.
+ * ``weak_disc`` and ``weak_disc2``) for the step to time t_n = n dt.
+ *   u_prev: device [N] u_{n-1};
+ *   gates:  device [n_gamma*3] (n, m, h) per membrane vertex, in: w_{n-1},
+ *           out: w_n after n_ode Rush-Larsen sub-steps at frozen phi_M^{n-1}
+ *           (Hodgkin-Huxley cells only; other rows untouched); NULL allowed
+ *           if no cell uses the Hodgkin-Huxley model;
+ *   theta:  device [n_cells] factors on every leak conductance of each cell's
+ *           membrane, or NULL for all 1;
+ *   f_out:  device [N] receives f_n (unscaled).
+ * A_{n-1} stays in the context, stored as S A S with S = diag(P_0)^{-1/2} fixed
+ * at the first call.  The first call also fixes P_0.  KNP_E_NUMERIC if u_prev
+ * holds a NaN or Inf. */
+knp_status knp_assemble_step(knp_ctx *ctx, double t_n, double dt, const double *u_prev,
+                             double *gates, const double *theta, double *f_out);
+
+/* Build the algebraic-multigrid hierarchy of P_0 (eq. ``P_prec``), frozen for all
+ * steps (same section).  Must follow the first knp_assemble_step (else
+ * KNP_E_STATE).  opts NULL = defaults (FP64, strength 0.25, Chebyshev degree 2 on
+ * [lmax/10, lmax], coarse_max 2000, max_levels 20). */
+knp_status knp_amg_setup(knp_ctx *ctx, const knp_amg_opts *opts);
+
+/* Solve A_{n-1} x = b with right-preconditioned flexible GMRES(restart) (the
+ * paper's GMRES with one V-cycle of AMG(P_0) per iteration).  b: device [N]
+ * (unscaled, e.g. f_n); x: device [N], in: initial guess (u_{n-1}), out: the
+ * solution.  opts NULL = rtol 1e-6, restart 30, max_it 2000, reorth 0, precond 1.
+ * Blocks until done.  KNP_E_NOCONV if max_it was reached (x is the last iterate). */
+knp_status knp_gmres_solve(knp_ctx *ctx, const double *b, double *x,
+                           const knp_solve_opts *opts, knp_solve_info *info);
+
+/* Solve the adjoint system A_{n-1}^T lambda = rhs with the same preconditioner
+ * (P_0 is symmetric).  Same conventions as knp_gmres_solve. */
+knp_status knp_adjoint_solve(knp_ctx *ctx, const double *rhs, double *lambda,
+                             const knp_solve_opts *opts, knp_solve_info *info);
+
+/* Vector-Jacobian products of the step residual R = A(u_prev, theta) u_n -
+ * f(u_prev, theta) for the assembled step: accumulates
+ *   u_prev_bar += (dR/du_prev)^T lambda_n   and   theta_bar += (dR/dtheta)^T lambda_n
+ * (both device; theta_bar may be NULL).  Must follow knp_assemble_step of the
+ * same step (same u_prev, gates and theta).  Passive-leak membranes only
+ * (KNP_E_ARG if a Hodgkin-Huxley cell is present). */
+knp_status knp_step_vjp(knp_ctx *ctx, const double *u_prev, const double *u_n,
+                        const double *lambda_n, double *u_prev_bar, double *theta_bar);
+
+/* Operator hooks for tests and measurement (device vectors of length N):
+ *   which 0: y = S A S x (the stored system matrix)
+ *   which 1: y = one V-cycle on S P_0 S applied to x
+ *   which 2: y = (S A S)^T x
+ * and S itself: knp_get_scaling copies diag(S) to device [N]. */
+knp_status knp_apply(knp_ctx *ctx, int which, const double *x, double *y);
+knp_status knp_get_scaling(knp_ctx *ctx, double *s);
+
+/* Copy the stored values S A S (device [nnz_A], pattern of knp_get_layout). */
+knp_status knp_get_values(knp_ctx *ctx, double *vals);
+
+/* Kernel timing for roofline measurement.  knp_timing(ctx, 1) resets the
+ * counters and starts bracketing the instrumented launches with HIP events on
+ * the context's stream; knp_timing(ctx, 0) stops.  knp_timing_read fills
+ * out[KNP_TIMER_COUNT]: per kernel class the number of launches, their summed
+ * device time (ms, from the events) and their summed algorithmic bytes (the
+ * bytes the kernel must move at least once: matrix values and indices, row
+ * pointers, each vector read or written once). */
+enum { KNP_TIMER_SPMV_A = 0,        /* y = (S A S) x, Krylov operator          */
+       KNP_TIMER_CHEB_L0 = 1,       /* Chebyshev step on the finest AMG level  */
+       KNP_TIMER_RESID_L0 = 2,      /* residual on the finest AMG level        */
+       KNP_TIMER_VCYCLE = 3,        /* one whole V-cycle                        */
+       KNP_TIMER_ASSEMBLY = 4,      /* knp_assemble_step device work            */
+       KNP_TIMER_COUNT = 5 };
+typedef struct {
+    int64_t launches;
+    double total_ms;
+    double bytes;
+} knp_timer;
+knp_status knp_timing(knp_ctx *ctx, int enable);
+knp_status knp_timing_read(knp_ctx *ctx, knp_timer *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KNP_H */

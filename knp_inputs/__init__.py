@@ -102,7 +102,7 @@ def structured_simplex_mesh(shape, length_um):
     is split into one simplex per axis permutation sigma, in lexicographic order,
     with vertices v0, v0+e_s1, v0+e_s1+e_s2, (v0+1,1,1).  In 2D this yields the
     lower-left to upper-right diagonal.
-    Returns (xyz [m], elem int32, cube index per element int64 [n_elem, dim]).
+    Returns (xyz [m], elem int32 [n_cube * d!, d+1]); element e lies in cube e // d!.
     """
     shape = tuple(int(s) for s in shape)
     dim = len(shape)
@@ -117,34 +117,36 @@ def structured_simplex_mesh(shape, length_um):
     strides = [1]
     for a in range(1, dim):
         strides.append(strides[-1] * nv[a - 1])
-    strides = np.array(strides, dtype=np.int64)
-
-    cube_idx = np.stack(np.meshgrid(*[np.arange(s) for s in shape], indexing="ij"), axis=-1)
-    cube_idx = cube_idx.transpose(tuple(reversed(range(dim))) + (dim,)).reshape(-1, dim)
-    v0 = cube_idx.astype(np.int64) @ strides
+    # lower-corner vertex of every cube, cubes in (z, y, x) order with x fastest
+    v0 = np.zeros([shape[a] for a in reversed(range(dim))], dtype=np.int64)
+    for a in range(dim):
+        idx = np.arange(shape[a], dtype=np.int64) * strides[a]
+        bshape = [1] * dim
+        bshape[dim - 1 - a] = shape[a]
+        v0 = v0 + idx.reshape(bshape)
+    v0 = v0.ravel()
     perms = list(itertools.permutations(range(dim)))
-    n_cube = cube_idx.shape[0]
-    elem = np.empty((n_cube, len(perms), dim + 1), dtype=np.int64)
+    elem = np.empty((v0.shape[0], len(perms), dim + 1), dtype=np.int32)
     for p, sigma in enumerate(perms):
         cur = v0.copy()
         elem[:, p, 0] = cur
         for q, ax in enumerate(sigma):
             cur = cur + strides[ax]
             elem[:, p, q + 1] = cur
-    elem = elem.reshape(-1, dim + 1)
-    cube_of_elem = np.repeat(cube_idx.astype(np.int64), len(perms), axis=0)
-    return xyz, elem.astype(np.int32), cube_of_elem
+    return xyz, elem.reshape(-1, dim + 1)
 
 
-def _tags_from_boxes(cube_of_elem, boxes):
+def _tags_from_boxes(shape, boxes):
     """Element belongs to cell c when its cube lies inside box c (grid indices)."""
-    tag = np.zeros(cube_of_elem.shape[0], dtype=np.int32)
+    dim = len(shape)
+    cube = np.zeros([shape[a] for a in reversed(range(dim))], dtype=np.int32)   # (z, y, x)
     for c, (lo, hi) in enumerate(boxes):
-        inside = np.all((cube_of_elem >= lo) & (cube_of_elem < hi), axis=1)
-        if np.any(tag[inside] != 0):
+        sl = tuple(slice(int(lo[a]), int(hi[a])) for a in reversed(range(dim)))
+        if np.any(cube[sl] != 0):
             raise ValueError("cells overlap")
-        tag[inside] = c + 1
-    return tag
+        cube[sl] = c + 1
+    n_perm = 2 if dim == 2 else 6
+    return np.repeat(cube.ravel(), n_perm)
 
 
 def _initial_concentrations(params, n_vert, seed):
@@ -184,9 +186,9 @@ def model_a_case(dim=2, nx=32, membrane="leak", dt=1e-4, n_steps=10, cfg_id=1,
         raise ValueError("nx must be divisible by 4 so the cell faces lie on grid planes")
     params = physical_params()
     shape = (nx,) * dim
-    xyz, elem, cube = structured_simplex_mesh(shape, (1.0,) * dim)
+    xyz, elem = structured_simplex_mesh(shape, (1.0,) * dim)
     boxes = np.array([[[nx // 4] * dim, [3 * nx // 4] * dim]], dtype=np.int64)
-    tag = _tags_from_boxes(cube, boxes)
+    tag = _tags_from_boxes(shape, boxes)
     hh = membrane == "hh"
     if stim is None:
         stim = hh
@@ -221,7 +223,7 @@ def lattice_case(cells=(4, 4, 4), pitch_um=(1.0, 1.0, 1.0), per_pitch=33, n_hh=1
     shape = tuple(c * n for c, n in zip(cells, per_axis))
     length = tuple(c * p for c, p in zip(cells, pitch_um))
     h = [L / s for L, s in zip(length, shape)]
-    xyz, elem, cube = structured_simplex_mesh(shape, length)
+    xyz, elem = structured_simplex_mesh(shape, length)
 
     rng_geo = np.random.Generator(np.random.PCG64(1000 + cfg_id))
     lattice = np.stack(np.meshgrid(*[np.arange(c) for c in cells], indexing="ij"), axis=-1)
@@ -245,7 +247,7 @@ def lattice_case(cells=(4, 4, 4), pitch_um=(1.0, 1.0, 1.0), per_pitch=33, n_hh=1
             sep = np.maximum(boxes[c1, 0] - boxes[c2, 1], boxes[c2, 0] - boxes[c1, 1])
             if np.max(sep) < 1:
                 raise ValueError("cells closer than one interval; increase per_pitch")
-    tag = _tags_from_boxes(cube, boxes)
+    tag = _tags_from_boxes(shape, boxes)
 
     n_cells = boxes.shape[0]
     rng_mem = np.random.Generator(np.random.PCG64(3000 + cfg_id))

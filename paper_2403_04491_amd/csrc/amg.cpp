@@ -1,0 +1,666 @@
+// Algebraic multigrid for the frozen block-diagonal preconditioner P_0
+// (eq. ``P_prec``; one V-cycle approximates P_0^{-1}, Sec. "Solution and
+// preconditioning strategy").
+//
+// Setup (host, once per run): smoothed aggregation.  The operator arrives
+// symmetrically scaled to unit diagonal.  Per level: strength of connection on
+// negative couplings relative to the row's largest, greedy three-phase
+// aggregation, tentative prolongator from the near-nullspace vector (the
+// constant in unscaled variables), one damped-Jacobi smoothing step on the
+// strength-filtered operator, Galerkin product R A P with R = P^T, and a
+// symmetric rescaling of the coarse operator to unit diagonal (absorbed into P
+// and R).  Aggregates never cross the blocks of P_0 because P_0 has no
+// couplings between them.  The coarsest level is solved with one dense FP64
+// inverse per connected component.
+//
+// Apply (device): V-cycle with Chebyshev pre/post smoothing, residual,
+// restriction and prolongation as fused CSR kernels, in FP64 or FP32 (FP32
+// accumulation); the coarsest solve is always FP64.
+#include <omp.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <type_traits>
+
+#include "knp_internal.h"
+
+namespace knp {
+
+namespace {
+
+Csr transpose(const Csr &A) {
+    Csr T;
+    T.nrows = A.ncols;
+    T.ncols = A.nrows;
+    T.rowptr.assign(T.nrows + 1, 0);
+    const int64_t nnz = A.nnz();
+    for (int64_t k = 0; k < nnz; ++k) T.rowptr[A.col[k] + 1]++;
+    for (int64_t i = 0; i < T.nrows; ++i) T.rowptr[i + 1] += T.rowptr[i];
+    T.col.resize(nnz);
+    T.val.resize(nnz);
+    std::vector<int64_t> fill(T.rowptr.begin(), T.rowptr.end() - 1);
+    for (int64_t i = 0; i < A.nrows; ++i)
+        for (int64_t k = A.rowptr[i]; k < A.rowptr[i + 1]; ++k) {
+            const int64_t p = fill[A.col[k]]++;
+            T.col[p] = int32_t(i);
+            T.val[p] = A.val[k];
+        }
+    return T;
+}
+
+// C = A B, rows computed independently (deterministic: accumulation follows the
+// order of A's row and B's rows); columns sorted per row.
+Csr spgemm(const Csr &A, const Csr &B) {
+    Csr C;
+    C.nrows = A.nrows;
+    C.ncols = B.ncols;
+    C.rowptr.assign(A.nrows + 1, 0);
+    const int nt = omp_get_max_threads();
+    std::vector<std::vector<int64_t>> marks(nt);
+#pragma omp parallel
+    {
+        std::vector<int64_t> &mk = marks[omp_get_thread_num()];
+        mk.assign(B.ncols, -1);
+#pragma omp for schedule(dynamic, 1024)
+        for (int64_t i = 0; i < A.nrows; ++i) {
+            int64_t cnt = 0;
+            for (int64_t ka = A.rowptr[i]; ka < A.rowptr[i + 1]; ++ka) {
+                const int32_t j = A.col[ka];
+                for (int64_t kb = B.rowptr[j]; kb < B.rowptr[j + 1]; ++kb) {
+                    const int32_t c = B.col[kb];
+                    if (mk[c] != i) {
+                        mk[c] = i;
+                        ++cnt;
+                    }
+                }
+            }
+            C.rowptr[i + 1] = cnt;
+        }
+    }
+    for (int64_t i = 0; i < A.nrows; ++i) C.rowptr[i + 1] += C.rowptr[i];
+    C.col.resize(C.rowptr[A.nrows]);
+    C.val.resize(C.rowptr[A.nrows]);
+#pragma omp parallel
+    {
+        std::vector<int64_t> pos(B.ncols, -1);
+        std::vector<int32_t> cols;
+        std::vector<double> acc(B.ncols, 0.0);
+#pragma omp for schedule(dynamic, 1024)
+        for (int64_t i = 0; i < A.nrows; ++i) {
+            cols.clear();
+            for (int64_t ka = A.rowptr[i]; ka < A.rowptr[i + 1]; ++ka) {
+                const int32_t j = A.col[ka];
+                const double a = A.val[ka];
+                for (int64_t kb = B.rowptr[j]; kb < B.rowptr[j + 1]; ++kb) {
+                    const int32_t c = B.col[kb];
+                    if (pos[c] != i) {
+                        pos[c] = i;
+                        acc[c] = 0.0;
+                        cols.push_back(c);
+                    }
+                    acc[c] += a * B.val[kb];
+                }
+            }
+            std::sort(cols.begin(), cols.end());
+            int64_t o = C.rowptr[i];
+            for (int32_t c : cols) {
+                C.col[o] = c;
+                C.val[o] = acc[c];
+                ++o;
+            }
+        }
+    }
+    return C;
+}
+
+double gershgorin(const Csr &A) {
+    double m = 0.0;
+#pragma omp parallel for reduction(max : m)
+    for (int64_t i = 0; i < A.nrows; ++i) {
+        double s = 0.0;
+        for (int64_t k = A.rowptr[i]; k < A.rowptr[i + 1]; ++k) s += std::fabs(A.val[k]);
+        m = std::max(m, s);
+    }
+    return m;
+}
+
+// power iteration on a symmetric unit-diagonal operator (deterministic start)
+double power_lmax(const Csr &A, int iters) {
+    const int64_t n = A.nrows;
+    std::vector<double> x(n), y(n);
+    for (int64_t i = 0; i < n; ++i) x[i] = 1.0 + 0.5 * std::sin(0.7 * double(i) + 0.3);
+    double lam = 0.0;
+    for (int it = 0; it < iters; ++it) {
+        double nx = 0.0;
+        for (int64_t i = 0; i < n; ++i) nx += x[i] * x[i];
+        nx = std::sqrt(nx);
+        for (int64_t i = 0; i < n; ++i) x[i] /= nx;
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < n; ++i) {
+            double s = 0.0;
+            for (int64_t k = A.rowptr[i]; k < A.rowptr[i + 1]; ++k) s += A.val[k] * x[A.col[k]];
+            y[i] = s;
+        }
+        double xy = 0.0;
+        for (int64_t i = 0; i < n; ++i) xy += x[i] * y[i];
+        lam = xy;
+        std::swap(x, y);
+    }
+    return lam;
+}
+
+// strong(i, j): a_ij < 0 and -a_ij >= theta * max_k(-a_ik)
+void strength(const Csr &A, double theta, std::vector<int64_t> &srow, std::vector<int32_t> &scol) {
+    const int64_t n = A.nrows;
+    srow.assign(n + 1, 0);
+    std::vector<double> thr(n, 0.0);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double m = 0.0;
+        int64_t cnt = 0;
+        for (int64_t k = A.rowptr[i]; k < A.rowptr[i + 1]; ++k)
+            if (A.col[k] != i) m = std::max(m, -A.val[k]);
+        thr[i] = theta * m;
+        if (m > 0.0)
+            for (int64_t k = A.rowptr[i]; k < A.rowptr[i + 1]; ++k)
+                if (A.col[k] != i && -A.val[k] >= thr[i] && A.val[k] < 0.0) ++cnt;
+        srow[i + 1] = cnt;
+    }
+    for (int64_t i = 0; i < n; ++i) srow[i + 1] += srow[i];
+    scol.resize(srow[n]);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t o = srow[i];
+        if (thr[i] > 0.0)
+            for (int64_t k = A.rowptr[i]; k < A.rowptr[i + 1]; ++k)
+                if (A.col[k] != i && -A.val[k] >= thr[i] && A.val[k] < 0.0) scol[o++] = A.col[k];
+    }
+}
+
+// three-phase greedy aggregation; returns number of aggregates
+int64_t aggregate(int64_t n, const std::vector<int64_t> &srow, const std::vector<int32_t> &scol,
+                  std::vector<int32_t> &agg) {
+    agg.assign(n, -1);
+    int64_t na = 0;
+    for (int64_t i = 0; i < n; ++i) {   // phase 1: root + all-free strong neighbourhood
+        if (agg[i] >= 0) continue;
+        bool free_nb = true;
+        for (int64_t k = srow[i]; k < srow[i + 1]; ++k)
+            if (agg[scol[k]] >= 0) {
+                free_nb = false;
+                break;
+            }
+        if (!free_nb || srow[i + 1] == srow[i]) continue;
+        agg[i] = int32_t(na);
+        for (int64_t k = srow[i]; k < srow[i + 1]; ++k) agg[scol[k]] = int32_t(na);
+        ++na;
+    }
+    std::vector<int32_t> agg1 = agg;
+    for (int64_t i = 0; i < n; ++i) {   // phase 2: join a neighbouring phase-1 aggregate
+        if (agg[i] >= 0) continue;
+        for (int64_t k = srow[i]; k < srow[i + 1]; ++k)
+            if (agg1[scol[k]] >= 0) {
+                agg[i] = agg1[scol[k]];
+                break;
+            }
+    }
+    for (int64_t i = 0; i < n; ++i) {   // phase 3: leftovers with their free neighbours
+        if (agg[i] >= 0) continue;
+        agg[i] = int32_t(na);
+        for (int64_t k = srow[i]; k < srow[i + 1]; ++k)
+            if (agg[scol[k]] < 0) agg[scol[k]] = int32_t(na);
+        ++na;
+    }
+    return na;
+}
+
+struct HostLevel {
+    Csr A, P, R;
+    double lmax;
+};
+
+void invert_dense(int n, std::vector<double> &a) {   // Gauss-Jordan, partial pivoting, in place
+    std::vector<int> piv(n);
+    std::vector<double> inv(size_t(n) * n, 0.0);
+    for (int i = 0; i < n; ++i) inv[size_t(i) * n + i] = 1.0;
+    for (int c = 0; c < n; ++c) {
+        int p = c;
+        for (int r = c + 1; r < n; ++r)
+            if (std::fabs(a[size_t(r) * n + c]) > std::fabs(a[size_t(p) * n + c])) p = r;
+        if (a[size_t(p) * n + c] == 0.0) throw Error{KNP_E_NUMERIC, "singular coarsest-level block"};
+        if (p != c)
+            for (int k = 0; k < n; ++k) {
+                std::swap(a[size_t(p) * n + k], a[size_t(c) * n + k]);
+                std::swap(inv[size_t(p) * n + k], inv[size_t(c) * n + k]);
+            }
+        const double d = 1.0 / a[size_t(c) * n + c];
+        for (int k = 0; k < n; ++k) {
+            a[size_t(c) * n + k] *= d;
+            inv[size_t(c) * n + k] *= d;
+        }
+        for (int r = 0; r < n; ++r) {
+            if (r == c) continue;
+            const double f = a[size_t(r) * n + c];
+            if (f == 0.0) continue;
+            for (int k = 0; k < n; ++k) {
+                a[size_t(r) * n + k] -= f * a[size_t(c) * n + k];
+                inv[size_t(r) * n + k] -= f * inv[size_t(c) * n + k];
+            }
+        }
+    }
+    a.swap(inv);
+}
+
+}  // namespace
+
+void DevCsr::upload(const Csr &h, bool fp32, hipStream_t s) {
+    nrows = h.nrows;
+    ncols = h.ncols;
+    nnz = h.nnz();
+    rowptr.alloc(h.rowptr.size());
+    rowptr.upload(h.rowptr, s);
+    col.alloc(std::max<size_t>(1, h.col.size()));
+    if (!h.col.empty()) col.upload(h.col, s);
+    if (fp32) {
+        std::vector<float> v(h.val.begin(), h.val.end());
+        val32.alloc(std::max<size_t>(1, v.size()));
+        if (!v.empty()) val32.upload(v, s);
+        hip_check(hipStreamSynchronize(s), "upload");
+    } else {
+        val64.alloc(std::max<size_t>(1, h.val.size()));
+        if (!h.val.empty()) val64.upload(h.val, s);
+    }
+}
+
+Amg::~Amg() { clear(); }
+
+void Amg::clear() {
+    for (Level *l : levels) delete l;
+    levels.clear();
+    ready = false;
+    level_nnz.clear();
+    level_n.clear();
+}
+
+void amg_build(Amg &amg, const HostMesh &m, const std::vector<double> &p0_vals, const std::vector<double> &near_null,
+               const knp_amg_opts &o, hipStream_t s) {
+    amg.clear();
+    amg.fp32 = o.precision == 1;
+    amg.degree = std::max(1, o.cheb_degree);
+    amg.ratio = o.cheb_ratio;
+    // P_0 in CSR: per (region, field) the scalar pattern of the region
+    Csr A;
+    A.nrows = A.ncols = m.N;
+    A.rowptr.assign(m.N + 1, 0);
+    for (int r = 0; r < 2; ++r)
+        for (int f = 0; f < 4; ++f)
+            for (int64_t j = 0; j < m.Nr[r]; ++j)
+                A.rowptr[m.off[r] + f * m.Nr[r] + j + 1] = m.prow[r][j + 1] - m.prow[r][j];
+    for (int64_t i = 0; i < m.N; ++i) A.rowptr[i + 1] += A.rowptr[i];
+    A.col.resize(A.rowptr[m.N]);
+    for (int r = 0; r < 2; ++r)
+        for (int f = 0; f < 4; ++f) {
+            const int64_t base = m.off[r] + f * m.Nr[r];
+#pragma omp parallel for schedule(static)
+            for (int64_t j = 0; j < m.Nr[r]; ++j) {
+                int64_t o2 = A.rowptr[base + j];
+                for (int64_t k = m.prow[r][j]; k < m.prow[r][j + 1]; ++k) A.col[o2++] = int32_t(base + m.pcol[r][k]);
+            }
+        }
+    A.val = p0_vals;
+    std::vector<double> B = near_null;
+
+    std::vector<HostLevel> H;
+    const int max_levels = std::max(1, o.max_levels);
+    const int64_t coarse_max = std::max<int32_t>(1, o.coarse_max);
+    while (true) {
+        HostLevel L;
+        L.A = std::move(A);
+        const int64_t n = L.A.nrows;
+        if (n <= coarse_max || int(H.size()) + 1 >= max_levels) {
+            H.push_back(std::move(L));
+            break;
+        }
+        std::vector<int64_t> srow;
+        std::vector<int32_t> scol;
+        strength(L.A, o.strength, srow, scol);
+        std::vector<int32_t> agg;
+        const int64_t nc = aggregate(n, srow, scol, agg);
+        if (double(nc) > 0.85 * double(n)) {   // coarsening stalled: make this the coarsest
+            H.push_back(std::move(L));
+            break;
+        }
+        // tentative prolongator from B
+        std::vector<double> bn(nc, 0.0);
+        for (int64_t i = 0; i < n; ++i) bn[agg[i]] += B[i] * B[i];
+        for (int64_t c = 0; c < nc; ++c) bn[c] = std::sqrt(bn[c]);
+        Csr T;
+        T.nrows = n;
+        T.ncols = nc;
+        T.rowptr.resize(n + 1);
+        T.col.resize(n);
+        T.val.resize(n);
+        for (int64_t i = 0; i < n; ++i) {
+            T.rowptr[i] = i;
+            T.col[i] = agg[i];
+            T.val[i] = bn[agg[i]] > 0.0 ? B[i] / bn[agg[i]] : 1.0;
+        }
+        T.rowptr[n] = n;
+        // filtered operator: diagonal + strong couplings, weak couplings lumped (B-weighted)
+        Csr AF;
+        AF.nrows = AF.ncols = n;
+        AF.rowptr.assign(n + 1, 0);
+        for (int64_t i = 0; i < n; ++i) AF.rowptr[i + 1] = AF.rowptr[i] + 1 + (srow[i + 1] - srow[i]);
+        AF.col.resize(AF.rowptr[n]);
+        AF.val.resize(AF.rowptr[n]);
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < n; ++i) {
+            double diag = 0.0, lump = 0.0;
+            int64_t ks = srow[i];
+            std::vector<std::pair<int32_t, double>> e;
+            for (int64_t k = L.A.rowptr[i]; k < L.A.rowptr[i + 1]; ++k) {
+                const int32_t j = L.A.col[k];
+                if (j == i) {
+                    diag = L.A.val[k];
+                } else if (ks < srow[i + 1] && scol[ks] == j) {
+                    e.push_back({j, L.A.val[k]});
+                    ++ks;
+                } else if (B[i] != 0.0) {
+                    lump += L.A.val[k] * B[j] / B[i];
+                }
+            }
+            double dF = diag + lump;
+            if (!(dF > 0.0)) dF = diag;
+            e.push_back({int32_t(i), dF});
+            std::sort(e.begin(), e.end());
+            int64_t oo = AF.rowptr[i];
+            for (auto &pr : e) {
+                AF.col[oo] = pr.first;
+                AF.val[oo] = pr.second;
+                ++oo;
+            }
+        }
+        // omega / rho(D_F^{-1} A_F) with a Gershgorin bound
+        double rho = 0.0;
+#pragma omp parallel for reduction(max : rho)
+        for (int64_t i = 0; i < n; ++i) {
+            double d = 0.0, sabs = 0.0;
+            for (int64_t k = AF.rowptr[i]; k < AF.rowptr[i + 1]; ++k) {
+                sabs += std::fabs(AF.val[k]);
+                if (AF.col[k] == i) d = AF.val[k];
+            }
+            if (d > 0.0) rho = std::max(rho, sabs / d);
+        }
+        const double omega = rho > 0.0 ? 4.0 / (3.0 * rho) : 0.0;
+        // P = (I - omega D_F^{-1} A_F) T
+        Csr DA = AF;
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < n; ++i) {
+            double d = 1.0;
+            for (int64_t k = AF.rowptr[i]; k < AF.rowptr[i + 1]; ++k)
+                if (AF.col[k] == i) d = AF.val[k];
+            for (int64_t k = DA.rowptr[i]; k < DA.rowptr[i + 1]; ++k) {
+                DA.val[k] = -omega * AF.val[k] / d;
+                if (DA.col[k] == i) DA.val[k] += 1.0;
+            }
+        }
+        Csr P = spgemm(DA, T);
+        Csr R = transpose(P);
+        Csr AP = spgemm(L.A, P);
+        Csr Ac = spgemm(R, AP);
+        // unit diagonal on the coarse level, absorbed into P and R
+        std::vector<double> dc(nc, 1.0);
+        for (int64_t c = 0; c < nc; ++c)
+            for (int64_t k = Ac.rowptr[c]; k < Ac.rowptr[c + 1]; ++k)
+                if (Ac.col[k] == c) dc[c] = Ac.val[k] > 0.0 ? 1.0 / std::sqrt(Ac.val[k]) : 1.0;
+#pragma omp parallel for schedule(static)
+        for (int64_t c = 0; c < nc; ++c)
+            for (int64_t k = Ac.rowptr[c]; k < Ac.rowptr[c + 1]; ++k) Ac.val[k] *= dc[c] * dc[Ac.col[k]];
+        for (int64_t k = 0; k < P.nnz(); ++k) P.val[k] *= dc[P.col[k]];
+        for (int64_t c = 0; c < nc; ++c)
+            for (int64_t k = R.rowptr[c]; k < R.rowptr[c + 1]; ++k) R.val[k] *= dc[c];
+        std::vector<double> Bc(nc);
+        for (int64_t c = 0; c < nc; ++c) Bc[c] = bn[c] / dc[c];
+        L.P = std::move(P);
+        L.R = std::move(R);
+        H.push_back(std::move(L));
+        A = std::move(Ac);
+        B.swap(Bc);
+    }
+
+    // spectral bounds for Chebyshev
+    for (auto &L : H) {
+        const double g = gershgorin(L.A);
+        const double pw = L.A.nrows > 1 ? 1.1 * power_lmax(L.A, 20) : g;
+        L.lmax = std::min(g, std::max(pw, 1e-12));
+    }
+
+    // coarsest level: connected components, dense inverses
+    const Csr &C = H.back().A;
+    const int64_t nC = C.nrows;
+    std::vector<int32_t> comp(nC, -1);
+    std::vector<int64_t> order;
+    order.reserve(nC);
+    std::vector<int64_t> cstart;
+    int32_t ncomp = 0;
+    for (int64_t i = 0; i < nC; ++i) {
+        if (comp[i] >= 0) continue;
+        cstart.push_back(int64_t(order.size()));
+        size_t head = order.size();
+        comp[i] = ncomp;
+        order.push_back(i);
+        while (head < order.size()) {
+            const int64_t v = order[head++];
+            for (int64_t k = C.rowptr[v]; k < C.rowptr[v + 1]; ++k) {
+                const int32_t w = C.col[k];
+                if (comp[w] < 0) {
+                    comp[w] = ncomp;
+                    order.push_back(w);
+                }
+            }
+        }
+        ++ncomp;
+    }
+    cstart.push_back(nC);
+    // component members in ascending row order; position of each row inside its component
+    for (int32_t c = 0; c < ncomp; ++c) std::sort(order.begin() + cstart[c], order.begin() + cstart[c + 1]);
+    std::vector<int32_t> cloc(nC), cmem(nC);
+    for (int32_t c = 0; c < ncomp; ++c)
+        for (int64_t p = cstart[c]; p < cstart[c + 1]; ++p) {
+            cmem[p] = int32_t(order[p]);
+            cloc[order[p]] = int32_t(p - cstart[c]);
+        }
+    std::vector<int64_t> boff(ncomp);
+    int64_t tot = 0;
+    for (int32_t c = 0; c < ncomp; ++c) {
+        const int64_t nb = cstart[c + 1] - cstart[c];
+        if (nb > 4096) throw Error{KNP_E_NOMEM, "coarsest-level component too large for a dense inverse"};
+        boff[c] = tot;
+        tot += nb * nb;
+    }
+    std::vector<double> inv(std::max<int64_t>(1, tot), 0.0);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int32_t c = 0; c < ncomp; ++c) {
+        const int64_t s0 = cstart[c], nb = cstart[c + 1] - s0;
+        std::vector<double> a(size_t(nb) * nb, 0.0);
+        for (int64_t p = 0; p < nb; ++p) {
+            const int64_t v = order[s0 + p];
+            for (int64_t k = C.rowptr[v]; k < C.rowptr[v + 1]; ++k) a[size_t(p) * nb + cloc[C.col[k]]] = C.val[k];
+        }
+        invert_dense(int(nb), a);
+        std::copy(a.begin(), a.end(), inv.begin() + boff[c]);
+    }
+
+    // upload
+    const bool f32 = amg.fp32;
+    for (size_t l = 0; l < H.size(); ++l) {
+        Level *L = new Level();
+        amg.levels.push_back(L);
+        L->n = H[l].A.nrows;
+        L->lmax = H[l].lmax;
+        amg.level_n.push_back(L->n);
+        amg.level_nnz.push_back(H[l].A.nnz());
+        const bool last = l + 1 == H.size();
+        if (!last) {
+            L->A.upload(H[l].A, f32, s);
+            L->P.upload(H[l].P, f32, s);
+            L->R.upload(H[l].R, f32, s);
+        }
+        const size_t n = size_t(std::max<int64_t>(1, L->n));
+        if (f32) {
+            L->b32.alloc(n);
+            L->x32.alloc(n);
+            L->t32.alloc(n);
+            L->d32.alloc(n);
+            L->x2_32.alloc(n);
+        } else {
+            L->b64.alloc(n);
+            L->x64.alloc(n);
+            L->t64.alloc(n);
+            L->d64.alloc(n);
+            L->x2_64.alloc(n);
+        }
+    }
+    amg.n_coarse = nC;
+    amg.n_blocks = ncomp;
+    amg.ccomp.alloc(std::max<int64_t>(1, nC));
+    amg.ccomp.upload(comp, s);
+    amg.cloc.alloc(std::max<int64_t>(1, nC));
+    amg.cloc.upload(cloc, s);
+    amg.cmem.alloc(std::max<int64_t>(1, nC));
+    amg.cmem.upload(cmem, s);
+    amg.cstart.alloc(cstart.size());
+    amg.cstart.upload(cstart, s);
+    amg.coff.alloc(std::max<size_t>(1, boff.size()));
+    amg.coff.upload(boff, s);
+    amg.cinv.alloc(inv.size());
+    amg.cinv.upload(inv, s);
+    amg.cb64.alloc(std::max<int64_t>(1, nC));
+    amg.cx64.alloc(std::max<int64_t>(1, nC));
+    hip_check(hipStreamSynchronize(s), "amg upload");
+    amg.ready = true;
+}
+
+namespace {
+
+// Chebyshev coefficients (c1, c2) of the three-term recurrence for the interval
+// [lmax/ratio, lmax]:  d <- c1 d + c2 r,  x <- x + d.
+void cheb_coeffs(double lmax, double ratio, int degree, std::vector<std::pair<double, double>> &out) {
+    const double a = lmax / ratio, b = lmax;
+    const double theta = 0.5 * (b + a), delta = 0.5 * (b - a), sigma = theta / delta;
+    double rho = 1.0 / sigma;
+    out.clear();
+    out.push_back({0.0, 1.0 / theta});
+    for (int k = 1; k < degree; ++k) {
+        const double rn = 1.0 / (2.0 * sigma - rho);
+        out.push_back({rn * rho, 2.0 * rn / delta});
+        rho = rn;
+    }
+}
+
+template <typename T>
+struct LV;
+template <>
+struct LV<double> {
+    static double *b(Level *L) { return L->b64.p; }
+    static double *x(Level *L) { return L->x64.p; }
+    static double *x2(Level *L) { return L->x2_64.p; }
+    static double *t(Level *L) { return L->t64.p; }
+    static double *d(Level *L) { return L->d64.p; }
+    static const double *A(Level *L) { return L->A.val64.p; }
+    static const double *P(Level *L) { return L->P.val64.p; }
+    static const double *R(Level *L) { return L->R.val64.p; }
+};
+template <>
+struct LV<float> {
+    static float *b(Level *L) { return L->b32.p; }
+    static float *x(Level *L) { return L->x32.p; }
+    static float *x2(Level *L) { return L->x2_32.p; }
+    static float *t(Level *L) { return L->t32.p; }
+    static float *d(Level *L) { return L->d32.p; }
+    static const float *A(Level *L) { return L->A.val32.p; }
+    static const float *P(Level *L) { return L->P.val32.p; }
+    static const float *R(Level *L) { return L->R.val32.p; }
+};
+
+// V-cycle on level l: solves approximately A_l x = b, with b and the result in
+// the level's own buffers; returns the buffer holding x.
+template <typename T>
+T *vcycle_level(Amg &amg, size_t l, const T *b, hipStream_t s, Timers *tm) {
+    Level *L = amg.levels[l];
+    if (l + 1 == amg.levels.size()) {
+        T *x = LV<T>::x(L);
+        if constexpr (std::is_same<T, double>::value) {
+            launch::coarse_solve(amg.n_coarse, amg.ccomp.p, amg.cloc.p, amg.cmem.p, amg.cstart.p, amg.coff.p, amg.cinv.p, b, x, s);
+        } else {
+            launch::convert<float, double>(amg.n_coarse, b, amg.cb64.p, s);
+            launch::coarse_solve(amg.n_coarse, amg.ccomp.p, amg.cloc.p, amg.cmem.p, amg.cstart.p, amg.coff.p,
+                                 amg.cinv.p, amg.cb64.p, amg.cx64.p, s);
+            launch::convert<double, float>(amg.n_coarse, amg.cx64.p, x, s);
+        }
+        return x;
+    }
+    std::vector<std::pair<double, double>> cc;
+    cheb_coeffs(L->lmax, amg.ratio, amg.degree, cc);
+    const int64_t n = L->n, nnz = L->A.nnz;
+    const int64_t *rp = L->A.rowptr.p;
+    const int32_t *ci = L->A.col.p;
+    const T *av = LV<T>::A(L);
+    T *x = LV<T>::x(L), *x2 = LV<T>::x2(L), *d = LV<T>::d(L), *t = LV<T>::t(L);
+    // algorithmic bytes: values + column indices once, row pointers, each vector once
+    const double vb = double(sizeof(T));
+    const double mat = double(nnz) * (vb + 4.0) + 8.0 * double(n + 1);
+    Timers *t0 = (l == 0) ? tm : nullptr;
+    auto cheb = [&](const T *xin, T *xout, double c1, double c2) {
+        hipEvent_t e = t0 ? t0->begin(KNP_TIMER_CHEB_L0, s) : nullptr;
+        launch::cheb_step<T>(n, rp, ci, av, xin, b, d, xout, c1, c2, nnz, s);
+        if (t0) {
+            const double bytes = xin ? mat + vb * double(n) * (c1 != 0.0 ? 5.0 : 4.0) : 3.0 * vb * double(n);
+            t0->end(KNP_TIMER_CHEB_L0, e, bytes, s);
+        }
+    };
+    // pre-smoothing from x = 0
+    cheb(nullptr, x, 0.0, cc[0].second);
+    for (size_t k = 1; k < cc.size(); ++k) {
+        cheb(x, x2, cc[k].first, cc[k].second);
+        std::swap(x, x2);
+    }
+    // residual and restriction
+    {
+        hipEvent_t e = t0 ? t0->begin(KNP_TIMER_RESID_L0, s) : nullptr;
+        launch::residual<T>(n, rp, ci, av, x, b, t, nnz, s);
+        if (t0) t0->end(KNP_TIMER_RESID_L0, e, mat + 3.0 * vb * double(n), s);
+    }
+    Level *Lc = amg.levels[l + 1];
+    T *bc = LV<T>::b(Lc);
+    launch::spmv<T, T, T>(L->R.nrows, L->R.rowptr.p, L->R.col.p, LV<T>::R(L), t, bc, L->R.nnz, s);
+    T *xc = vcycle_level<T>(amg, l + 1, bc, s, tm);
+    launch::prolong_add<T>(n, L->P.rowptr.p, L->P.col.p, LV<T>::P(L), xc, x, L->P.nnz, s);
+    // post-smoothing
+    for (size_t k = 0; k < cc.size(); ++k) {
+        cheb(x, x2, cc[k].first, cc[k].second);
+        std::swap(x, x2);
+    }
+    return x;
+}
+
+}  // namespace
+
+void amg_vcycle(Amg &amg, const double *v, void *z, hipStream_t s, Timers *tm) {
+    Level *L0 = amg.levels[0];
+    const int64_t n = L0->n;
+    hipEvent_t e = tm ? tm->begin(KNP_TIMER_VCYCLE, s) : nullptr;
+    if (amg.fp32) {
+        launch::convert<double, float>(n, v, L0->b32.p, s);
+        float *x = vcycle_level<float>(amg, 0, L0->b32.p, s, tm);
+        hip_check(hipMemcpyAsync(z, x, size_t(n) * sizeof(float), hipMemcpyDeviceToDevice, s), "vcycle copy");
+    } else {
+        double *x = vcycle_level<double>(amg, 0, v, s, tm);
+        hip_check(hipMemcpyAsync(z, x, size_t(n) * sizeof(double), hipMemcpyDeviceToDevice, s), "vcycle copy");
+    }
+    if (tm) tm->end(KNP_TIMER_VCYCLE, e, 0.0, s);
+}
+
+}  // namespace knp

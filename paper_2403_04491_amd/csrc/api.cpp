@@ -1,0 +1,618 @@
+// The C entry points of libknp (declared in include/knp.h).  Each call checks
+// its arguments, converts every internal failure into a status code plus a
+// message, and never lets a C++ exception cross the ABI.
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "ctx.h"
+
+namespace knp {
+
+void hip_check(hipError_t e, const char *what) {
+    if (e != hipSuccess) throw Error{KNP_E_HIP, std::string(what) + ": " + hipGetErrorString(e)};
+}
+
+template <typename T>
+void DArray<T>::alloc(size_t count) {
+    release();
+    if (count == 0) count = 1;
+    void *ptr = nullptr;
+    hipError_t e = hipMalloc(&ptr, count * sizeof(T));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        throw Error{KNP_E_NOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed"};
+    }
+    p = static_cast<T *>(ptr);
+    n = count;
+}
+
+template <typename T>
+void DArray<T>::upload(const T *h, size_t count, hipStream_t s) {
+    if (count == 0) return;
+    if (count > n) throw Error{KNP_E_ARG, "internal: upload larger than buffer"};
+    hip_check(hipMemcpyAsync(p, h, count * sizeof(T), hipMemcpyHostToDevice, s), "upload");
+    hip_check(hipStreamSynchronize(s), "upload sync");
+}
+
+template <typename T>
+void DArray<T>::download(T *h, size_t count, hipStream_t s) const {
+    if (count == 0) return;
+    hip_check(hipMemcpyAsync(h, p, count * sizeof(T), hipMemcpyDeviceToHost, s), "download");
+    hip_check(hipStreamSynchronize(s), "download sync");
+}
+
+hipEvent_t Timers::begin(int k, hipStream_t s) {
+    (void)k;
+    if (!on) return nullptr;
+    hipEvent_t e;
+    if (!pool.empty()) {
+        e = pool.back();
+        pool.pop_back();
+    } else {
+        hip_check(hipEventCreate(&e), "event create");
+    }
+    hip_check(hipEventRecord(e, s), "event record");
+    return e;
+}
+
+void Timers::end(int k, hipEvent_t start, double bytes, hipStream_t s) {
+    if (!on || !start) return;
+    hipEvent_t e = begin(k, s);
+    cls[k].a.push_back(start);
+    cls[k].b.push_back(e);
+    cls[k].bytes.push_back(bytes);
+}
+
+void Timers::harvest() {
+    for (auto &c : cls) {
+        for (size_t i = 0; i < c.a.size(); ++i) {
+            float ms = 0.0f;
+            hip_check(hipEventElapsedTime(&ms, c.a[i], c.b[i]), "event elapsed");
+            c.ms += ms;
+            c.launches += 1;
+            c.total_bytes += c.bytes[i];
+            pool.push_back(c.a[i]);
+            pool.push_back(c.b[i]);
+        }
+        c.a.clear();
+        c.b.clear();
+        c.bytes.clear();
+    }
+}
+
+void Timers::reset() {
+    for (auto &c : cls) {
+        for (auto e : c.a) pool.push_back(e);
+        for (auto e : c.b) pool.push_back(e);
+        c = Cls();
+    }
+}
+
+Timers::~Timers() {
+    reset();
+    for (auto e : pool) (void)hipEventDestroy(e);
+}
+
+template struct DArray<double>;
+template struct DArray<float>;
+template struct DArray<int32_t>;
+template struct DArray<int64_t>;
+template struct DArray<uint32_t>;
+
+}  // namespace knp
+
+using namespace knp;
+
+knp::launch::RegionArgs knp_ctx::region(int r) const {
+    knp::launch::RegionArgs a{};
+    a.r = r;
+    a.dim = hm.dim;
+    a.Nr = hm.Nr[r];
+    a.off = hm.off[r];
+    a.off_q = hm.off[1 - r];
+    a.Nq = hm.Nr[1 - r];
+    a.prow = d_prow[r].p;
+    a.pcol = d_pcol[r].p;
+    a.irow = d_irow[r].p;
+    a.ielem = d_ielem[r].p;
+    a.ipos = d_ipos[r].p;
+    a.verts = d_verts[r].p;
+    return a;
+}
+
+knp::launch::MeshArgs knp_ctx::mesh_args() const {
+    knp::launch::MeshArgs a{};
+    a.dim = hm.dim;
+    a.xyz = d_xyz.p;
+    a.elem = d_elem.p;
+    a.loc_i = d_loc[0].p;
+    a.loc_e = d_loc[1].p;
+    return a;
+}
+
+knp::launch::GammaArgs knp_ctx::gamma_args() const {
+    knp::launch::GammaArgs g{};
+    g.n_gamma = int64_t(hm.gamma.size());
+    g.gamma = d_gamma.p;
+    g.gloc_i = d_gloc_i.p;
+    g.gloc_e = d_gloc_e.p;
+    g.gcell = d_gcell.p;
+    g.frow = d_frow.p;
+    g.ffacet = d_ffacet.p;
+    g.fpos_i = d_fpos[0].p;
+    g.fpos_e = d_fpos[1].p;
+    g.facets = d_facets.p;
+    g.gidx = d_gidx.p;
+    g.cell_model = d_cell_model.p;
+    g.cell_stim = d_cell_stim.p;
+    return g;
+}
+
+knp::launch::PhysArgs knp_ctx::phys(double t, double dt) const {
+    knp::launch::PhysArgs p{};
+    const double psi = prm.R * prm.T / prm.F;
+    for (int k = 0; k < 3; ++k) {
+        p.z[k] = prm.z[k];
+        p.D[k] = prm.D[k];
+        p.tau[k] = dt * prm.D[k];
+        p.ttau[k] = p.tau[k] * prm.z[k] / psi;
+        p.g_leak[k] = prm.g_leak[k];
+    }
+    p.F = prm.F;
+    p.C_m = prm.C_m;
+    p.psi = psi;
+    p.dt = dt;
+    p.t = t;
+    p.gbar_Na = prm.gbar_Na;
+    p.gbar_K = prm.gbar_K;
+    p.g_stim_bar = prm.g_stim_bar;
+    p.stim_a = prm.stim_a;
+    p.stim_tau = prm.stim_tau;
+    p.phi_rest = prm.phi_rest;
+    p.n_ode = prm.n_ode;
+    return p;
+}
+
+namespace {
+
+knp_status fail(knp_ctx *c, knp_status st, const std::string &msg) {
+    if (c) c->err = msg;
+    return st;
+}
+
+template <typename F>
+knp_status guarded(knp_ctx *c, F &&fn) {
+    if (!c) return KNP_E_ARG;
+    try {
+        c->err.clear();
+        return fn();
+    } catch (const Error &e) {
+        return fail(c, e.st, e.msg);
+    } catch (const std::bad_alloc &) {
+        return fail(c, KNP_E_NOMEM, "host allocation failed");
+    } catch (const std::exception &e) {
+        return fail(c, KNP_E_ARG, e.what());
+    } catch (...) {
+        return fail(c, KNP_E_ARG, "unknown error");
+    }
+}
+
+void need_device(knp_ctx *c) {
+    if (c->host_only) throw Error{KNP_E_STATE, "host-only context (created with device -1)"};
+}
+
+}  // namespace
+
+extern "C" {
+
+knp_status knp_create(knp_ctx **out, int hip_device, void *hip_stream) {
+    if (!out) return KNP_E_ARG;
+    *out = nullptr;
+    knp_ctx *c = new (std::nothrow) knp_ctx();
+    if (!c) return KNP_E_NOMEM;
+    c->device = hip_device;
+    c->host_only = hip_device < 0;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    if (!c->host_only) {
+        int n = 0;
+        if (hipGetDeviceCount(&n) != hipSuccess || hip_device >= n) {
+            delete c;
+            return KNP_E_HIP;
+        }
+        if (hipSetDevice(hip_device) != hipSuccess) {
+            delete c;
+            return KNP_E_HIP;
+        }
+        try {
+            c->d_flag.alloc(1);
+        } catch (...) {
+            delete c;
+            return KNP_E_NOMEM;
+        }
+    }
+    *out = c;
+    return KNP_OK;
+}
+
+void knp_destroy(knp_ctx *c) {
+    if (!c) return;
+    if (!c->host_only) {
+        (void)hipSetDevice(c->device);
+        (void)hipStreamSynchronize(c->stream);
+    }
+    delete c;
+}
+
+const char *knp_last_error(const knp_ctx *c) { return c ? c->err.c_str() : "NULL context"; }
+
+knp_status knp_mesh_upload(knp_ctx *c, int dim, int64_t n_vert, const double *xyz, int64_t n_elem,
+                           const int32_t *elem_vert, const int32_t *elem_tag, int64_t pin_vertex,
+                           knp_mesh_info *out) {
+    return guarded(c, [&]() -> knp_status {
+        if (c->have_mesh) return fail(c, KNP_E_STATE, "mesh already uploaded");
+        HostMesh m;
+        build_host_mesh(m, dim, n_vert, xyz, n_elem, elem_vert, elem_tag, pin_vertex);
+        c->hm = std::move(m);
+        HostMesh &h = c->hm;
+        if (!c->host_only) {
+            hip_check(hipSetDevice(c->device), "set device");
+            hipStream_t s = c->stream;
+            c->d_xyz.alloc(h.xyz.size());
+            c->d_xyz.upload(h.xyz, s);
+            c->d_elem.alloc(h.elem.size());
+            c->d_elem.upload(h.elem, s);
+            for (int r = 0; r < 2; ++r) {
+                c->d_loc[r].alloc(h.loc[r].size());
+                c->d_loc[r].upload(h.loc[r], s);
+                c->d_verts[r].alloc(h.verts[r].size());
+                c->d_verts[r].upload(h.verts[r], s);
+                c->d_prow[r].alloc(h.prow[r].size());
+                c->d_prow[r].upload(h.prow[r], s);
+                c->d_pcol[r].alloc(h.pcol[r].size());
+                c->d_pcol[r].upload(h.pcol[r], s);
+                c->d_irow[r].alloc(h.irow[r].size());
+                c->d_irow[r].upload(h.irow[r], s);
+                c->d_ielem[r].alloc(h.ielem[r].size());
+                c->d_ielem[r].upload(h.ielem[r], s);
+                c->d_ipos[r].alloc(h.ipos[r].size());
+                c->d_ipos[r].upload(h.ipos[r], s);
+                c->d_fpos[r].alloc(h.fpos[r].size());
+                c->d_fpos[r].upload(h.fpos[r], s);
+            }
+            const size_t ng = h.gamma.size();
+            std::vector<int32_t> gli(ng), gle(ng), gcell(ng);
+            for (size_t g = 0; g < ng; ++g) {
+                gli[g] = h.loc[0][h.gamma[g]];
+                gle[g] = h.loc[1][h.gamma[g]];
+                gcell[g] = h.vcell[h.gamma[g]];
+            }
+            c->d_gamma.alloc(ng);
+            c->d_gamma.upload(h.gamma, s);
+            c->d_gloc_i.alloc(ng);
+            c->d_gloc_i.upload(gli, s);
+            c->d_gloc_e.alloc(ng);
+            c->d_gloc_e.upload(gle, s);
+            c->d_gcell.alloc(ng);
+            c->d_gcell.upload(gcell, s);
+            c->d_frow.alloc(h.frow.size());
+            c->d_frow.upload(h.frow, s);
+            c->d_ffacet.alloc(h.ffacet.size());
+            c->d_ffacet.upload(h.ffacet, s);
+            c->d_facets.alloc(h.facets.size());
+            c->d_facets.upload(h.facets, s);
+            c->d_gidx.alloc(h.gidx.size());
+            c->d_gidx.upload(h.gidx, s);
+            c->d_gcoef.alloc(std::max<size_t>(1, ng) * GC_STRIDE);
+            c->d_rowptr.alloc(h.rowptr.size());
+            c->d_rowptr.upload(h.rowptr, s);
+            c->d_colidx.alloc(h.colidx.size());
+            c->d_colidx.upload(h.colidx, s);
+            c->d_diag.alloc(h.diag_pos.size());
+            c->d_diag.upload(h.diag_pos, s);
+            c->d_vals.alloc(h.nnz);
+            c->d_sc.alloc(h.N);
+            c->nblk = launch::reduce_blocks(h.N);
+            c->partial.alloc(size_t(c->nblk) * 16);
+            c->w.alloc(h.N);
+            c->bh.alloc(h.N);
+            c->yh.alloc(h.N);
+            c->dscal.alloc(64);
+            // algorithmic bytes of one per-step assembly: u_prev and f, the
+            // per-step values (phi columns of every row), incidence lists,
+            // element connectivity and coordinates, each touched once
+            {
+                double b = 16.0 * double(h.N);
+                for (int r = 0; r < 2; ++r) {
+                    b += 8.0 * 4.0 * double(h.prow[r][h.Nr[r]]);
+                    b += 8.0 * double(h.Nr[r] + 1) + 8.0 * double(h.irow[r][h.Nr[r]]);
+                }
+                b += 4.0 * double(h.elem.size()) + 8.0 * double(h.xyz.size());
+                c->assembly_bytes = b;
+            }
+            // element and incidence data stay; host copies of the big incidence
+            // arrays are no longer needed
+            for (int r = 0; r < 2; ++r) {
+                std::vector<int32_t>().swap(h.ielem[r]);
+                std::vector<uint32_t>().swap(h.ipos[r]);
+                std::vector<int64_t>().swap(h.irow[r]);
+            }
+        }
+        c->have_mesh = true;
+        if (out) {
+            out->n_vert = h.n_vert;
+            out->n_elem = h.n_elem;
+            out->N_i = h.Nr[0];
+            out->N_e = h.Nr[1];
+            out->N = h.N;
+            out->nnz_A = h.nnz;
+            out->nnz_P0 = h.nnz_p0;
+            out->n_gamma = int64_t(h.gamma.size());
+            out->n_facets = h.n_facets;
+            out->n_cells = h.n_cells;
+            out->dim = h.dim;
+            out->pin_dof = h.pin_dof;
+        }
+        return KNP_OK;
+    });
+}
+
+knp_status knp_get_layout(knp_ctx *c, int64_t *rowptr, int32_t *colidx, int32_t *dof_vertex) {
+    return guarded(c, [&]() -> knp_status {
+        if (!c->have_mesh) return fail(c, KNP_E_STATE, "no mesh");
+        const HostMesh &h = c->hm;
+        if (rowptr) std::memcpy(rowptr, h.rowptr.data(), h.rowptr.size() * sizeof(int64_t));
+        if (colidx) std::memcpy(colidx, h.colidx.data(), h.colidx.size() * sizeof(int32_t));
+        if (dof_vertex)
+            for (int r = 0; r < 2; ++r)
+                for (int f = 0; f < 4; ++f)
+                    for (int64_t j = 0; j < h.Nr[r]; ++j) dof_vertex[h.off[r] + f * h.Nr[r] + j] = h.verts[r][j];
+        return KNP_OK;
+    });
+}
+
+knp_status knp_get_gamma(knp_ctx *c, int32_t *gamma_vertex) {
+    return guarded(c, [&]() -> knp_status {
+        if (!c->have_mesh) return fail(c, KNP_E_STATE, "no mesh");
+        if (!gamma_vertex) return fail(c, KNP_E_ARG, "NULL output");
+        std::memcpy(gamma_vertex, c->hm.gamma.data(), c->hm.gamma.size() * sizeof(int32_t));
+        return KNP_OK;
+    });
+}
+
+knp_status knp_set_params(knp_ctx *c, const knp_params *p) {
+    return guarded(c, [&]() -> knp_status {
+        need_device(c);
+        if (!c->have_mesh) return fail(c, KNP_E_STATE, "knp_mesh_upload must come first");
+        if (!p) return fail(c, KNP_E_ARG, "NULL params");
+        if (p->n_cells != c->hm.n_cells) return fail(c, KNP_E_ARG, "n_cells does not match the mesh");
+        if (p->n_cells > 0 && (!p->cell_model || !p->cell_stim)) return fail(c, KNP_E_ARG, "NULL cell arrays");
+        if (!(p->F > 0 && p->R > 0 && p->T > 0 && p->C_m > 0) || p->n_ode < 1)
+            return fail(c, KNP_E_ARG, "invalid physical constants");
+        for (int k = 0; k < 3; ++k)
+            if (p->z[k] == 0.0 || !(p->D[k] > 0.0)) return fail(c, KNP_E_ARG, "invalid valence or diffusivity");
+        c->prm = *p;
+        c->cell_model.assign(p->cell_model, p->cell_model + p->n_cells);
+        c->cell_stim.assign(p->cell_stim, p->cell_stim + p->n_cells);
+        c->any_hh = false;
+        for (int32_t m : c->cell_model) c->any_hh |= (m == 1);
+        c->prm.cell_model = nullptr;
+        c->prm.cell_stim = nullptr;
+        std::vector<int32_t> cm = c->cell_model, cs = c->cell_stim;
+        if (cm.empty()) {
+            cm.push_back(0);
+            cs.push_back(0);
+        }
+        c->d_cell_model.alloc(cm.size());
+        c->d_cell_model.upload(cm, c->stream);
+        c->d_cell_stim.alloc(cs.size());
+        c->d_cell_stim.upload(cs, c->stream);
+        c->have_params = true;
+        return KNP_OK;
+    });
+}
+
+knp_status knp_assemble_step(knp_ctx *c, double t_n, double dt, const double *u_prev, double *gates,
+                             const double *theta, double *f_out) {
+    return guarded(c, [&]() -> knp_status {
+        need_device(c);
+        if (!c->have_mesh || !c->have_params) return fail(c, KNP_E_STATE, "mesh and params are required");
+        if (!u_prev || !f_out) return fail(c, KNP_E_ARG, "NULL u_prev or f_out");
+        if (c->any_hh && !gates) return fail(c, KNP_E_ARG, "gates required for Hodgkin-Huxley cells");
+        if (!(dt > 0.0) || !std::isfinite(t_n)) return fail(c, KNP_E_ARG, "invalid dt or t_n");
+        hip_check(hipSetDevice(c->device), "set device");
+        const HostMesh &h = c->hm;
+        hipStream_t s = c->stream;
+        int flag = 0;
+        hip_check(hipMemsetAsync(c->d_flag.p, 0, sizeof(int), s), "flag");
+        launch::check_finite(u_prev, h.N, c->d_flag.p, s);
+        hip_check(hipMemcpyAsync(&flag, c->d_flag.p, sizeof(int), hipMemcpyDeviceToHost, s), "flag copy");
+        hip_check(hipStreamSynchronize(s), "flag sync");
+        if (flag) return fail(c, KNP_E_NUMERIC, "NaN or Inf in u_prev");
+        const bool first = !c->assembled;
+        if (first) {
+            std::vector<double> ones(h.N, 1.0);
+            c->d_sc.upload(ones, s);
+        }
+        hipEvent_t t0 = c->tm.begin(KNP_TIMER_ASSEMBLY, s);
+        const auto p = c->phys(t_n, dt);
+        const auto ma = c->mesh_args();
+        const auto ga = c->gamma_args();
+        launch::membrane_coefficients(ga, p, h.Nr[0], h.Nr[1], u_prev, gates, theta, c->d_gcoef.p, s);
+        if (dt != c->dt_static) {
+            for (int r = 0; r < 2; ++r)
+                launch::assemble_static(c->region(r), ma, p, c->d_rowptr.p, c->d_vals.p, c->d_sc.p, h.pin_dof, s);
+            c->dt_static = dt;
+        }
+        for (int r = 0; r < 2; ++r)
+            launch::assemble_dynamic(c->region(r), ma, p, c->d_rowptr.p, c->d_vals.p, c->d_sc.p, u_prev, f_out,
+                                     h.pin_dof, s);
+        launch::assemble_membrane(ga, ma, p, h.Nr[0], h.Nr[1], c->d_prow[0].p, c->d_prow[1].p, c->d_rowptr.p,
+                                  c->d_colidx.p, c->d_vals.p, c->d_sc.p, c->d_gcoef.p, f_out, s);
+        c->tm.end(KNP_TIMER_ASSEMBLY, t0, c->assembly_bytes, s);
+        if (first) {
+            launch::scaling_from_diag(h.N, c->d_vals.p, c->d_diag.p, c->d_sc.p, s);
+            launch::rescale_system(h.N, c->d_rowptr.p, c->d_colidx.p, c->d_vals.p, c->d_sc.p, s);
+            // P_0: the diagonal blocks of the first (scaled) matrix, kept on the host for AMG setup
+            std::vector<double> vals(h.nnz), sc(h.N);
+            c->d_vals.download(vals.data(), h.nnz, s);
+            c->d_sc.download(sc.data(), h.N, s);
+            c->p0_vals.resize(h.nnz_p0);
+            int64_t o = 0;
+            for (int r = 0; r < 2; ++r)
+                for (int f = 0; f < 4; ++f)
+                    for (int64_t j = 0; j < h.Nr[r]; ++j) {
+                        const int64_t row = h.off[r] + f * h.Nr[r] + j;
+                        const int64_t n = h.prow[r][j + 1] - h.prow[r][j];
+                        const int64_t len = h.rowptr[row + 1] - h.rowptr[row];
+                        const int64_t g = len - (f < 3 ? 2 : 4) * n;
+                        const int64_t seg = h.rowptr[row] + (r == 0 ? 0 : g) + (f < 3 ? 0 : 3 * n);
+                        for (int64_t q = 0; q < n; ++q) c->p0_vals[o++] = vals[seg + q];
+                    }
+            c->near_null.resize(h.N);
+            for (int64_t i = 0; i < h.N; ++i) c->near_null[i] = 1.0 / sc[i];
+            c->dt_first = dt;
+        }
+        hip_check(hipGetLastError(), "assembly launch");
+        hip_check(hipStreamSynchronize(s), "assembly");
+        c->tm.harvest();
+        c->assembled = true;
+        c->T_current = false;
+        return KNP_OK;
+    });
+}
+
+knp_status knp_amg_setup(knp_ctx *c, const knp_amg_opts *opts) {
+    return guarded(c, [&]() -> knp_status {
+        need_device(c);
+        if (!c->assembled) return fail(c, KNP_E_STATE, "knp_assemble_step must come first");
+        knp_amg_opts o{0, 0.25, 2, 10.0, 2000, 20};
+        if (opts) o = *opts;
+        if (o.precision != 0 && o.precision != 1) return fail(c, KNP_E_ARG, "precision must be 0 or 1");
+        if (!(o.strength > 0.0 && o.strength < 1.0) || o.cheb_degree < 1 || !(o.cheb_ratio > 1.0) ||
+            o.coarse_max < 1 || o.max_levels < 1)
+            return fail(c, KNP_E_ARG, "invalid AMG options");
+        hip_check(hipSetDevice(c->device), "set device");
+        amg_build(c->amg, c->hm, c->p0_vals, c->near_null, o, c->stream);
+        c->m_alloc = -1;   // Z precision may change
+        return KNP_OK;
+    });
+}
+
+static knp_status solve_common(knp_ctx *c, bool transpose, const double *b, double *x, const knp_solve_opts *opts,
+                               knp_solve_info *info) {
+    return guarded(c, [&]() -> knp_status {
+        need_device(c);
+        if (!c->assembled) return fail(c, KNP_E_STATE, "no assembled system");
+        if (!b || !x) return fail(c, KNP_E_ARG, "NULL vector");
+        knp_solve_opts o{1e-6, 30, 2000, 0, 1};
+        if (opts) o = *opts;
+        if (!(o.rtol >= 0.0) || o.restart < 1 || o.restart > 4096 || o.max_it < 0 ||
+            (o.precond != 0 && o.precond != 1))
+            return fail(c, KNP_E_ARG, "invalid solver options");
+        hip_check(hipSetDevice(c->device), "set device");
+        return krylov_solve(c, transpose, b, x, o, info);
+    });
+}
+
+knp_status knp_gmres_solve(knp_ctx *c, const double *b, double *x, const knp_solve_opts *opts,
+                           knp_solve_info *info) {
+    return solve_common(c, false, b, x, opts, info);
+}
+
+knp_status knp_adjoint_solve(knp_ctx *c, const double *rhs, double *lambda, const knp_solve_opts *opts,
+                             knp_solve_info *info) {
+    return solve_common(c, true, rhs, lambda, opts, info);
+}
+
+knp_status knp_apply(knp_ctx *c, int which, const double *x, double *y) {
+    return guarded(c, [&]() -> knp_status {
+        need_device(c);
+        if (!c->assembled) return fail(c, KNP_E_STATE, "no assembled system");
+        if (!x || !y) return fail(c, KNP_E_ARG, "NULL vector");
+        hip_check(hipSetDevice(c->device), "set device");
+        if (which == 0) {
+            apply_operator(c, false, x, y);
+        } else if (which == 1) {
+            if (!c->amg.ready) return fail(c, KNP_E_STATE, "knp_amg_setup has not been called");
+            if (c->amg.fp32) {
+                knp::DArray<float> z;
+                z.alloc(c->hm.N);
+                amg_vcycle(c->amg, x, z.p, c->stream, &c->tm);
+                launch::convert<float, double>(c->hm.N, z.p, y, c->stream);
+                hip_check(hipStreamSynchronize(c->stream), "apply");
+            } else {
+                amg_vcycle(c->amg, x, y, c->stream, &c->tm);
+            }
+        } else if (which == 2) {
+            ensure_transpose(c);
+            apply_operator(c, true, x, y);
+        } else {
+            return fail(c, KNP_E_ARG, "which must be 0, 1 or 2");
+        }
+        hip_check(hipStreamSynchronize(c->stream), "apply");
+        return KNP_OK;
+    });
+}
+
+knp_status knp_get_scaling(knp_ctx *c, double *s) {
+    return guarded(c, [&]() -> knp_status {
+        need_device(c);
+        if (!c->assembled) return fail(c, KNP_E_STATE, "no assembled system");
+        if (!s) return fail(c, KNP_E_ARG, "NULL output");
+        hip_check(hipMemcpyAsync(s, c->d_sc.p, sizeof(double) * c->hm.N, hipMemcpyDeviceToDevice, c->stream), "copy");
+        hip_check(hipStreamSynchronize(c->stream), "sync");
+        return KNP_OK;
+    });
+}
+
+knp_status knp_get_values(knp_ctx *c, double *vals) {
+    return guarded(c, [&]() -> knp_status {
+        need_device(c);
+        if (!c->assembled) return fail(c, KNP_E_STATE, "no assembled system");
+        if (!vals) return fail(c, KNP_E_ARG, "NULL output");
+        hip_check(hipMemcpyAsync(vals, c->d_vals.p, sizeof(double) * c->hm.nnz, hipMemcpyDeviceToDevice, c->stream),
+                  "copy");
+        hip_check(hipStreamSynchronize(c->stream), "sync");
+        return KNP_OK;
+    });
+}
+
+knp_status knp_timing(knp_ctx *c, int enable) {
+    return guarded(c, [&]() -> knp_status {
+        need_device(c);
+        hip_check(hipStreamSynchronize(c->stream), "sync");
+        c->tm.reset();
+        c->tm.on = enable != 0;
+        return KNP_OK;
+    });
+}
+
+knp_status knp_timing_read(knp_ctx *c, knp_timer *out) {
+    return guarded(c, [&]() -> knp_status {
+        need_device(c);
+        if (!out) return fail(c, KNP_E_ARG, "NULL output");
+        hip_check(hipStreamSynchronize(c->stream), "sync");
+        c->tm.harvest();
+        for (int k = 0; k < KNP_TIMER_COUNT; ++k) {
+            out[k].launches = c->tm.cls[k].launches;
+            out[k].total_ms = c->tm.cls[k].ms;
+            out[k].bytes = c->tm.cls[k].total_bytes;
+        }
+        return KNP_OK;
+    });
+}
+
+knp_status knp_step_vjp(knp_ctx *c, const double *u_prev, const double *u_n, const double *lambda_n,
+                        double *u_prev_bar, double *theta_bar) {
+    return guarded(c, [&]() -> knp_status {
+        (void)u_prev;
+        (void)u_n;
+        (void)lambda_n;
+        (void)u_prev_bar;
+        (void)theta_bar;
+        return fail(c, KNP_E_STATE, "knp_step_vjp: not available in this build");
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,563 @@
+// Assembly kernels for the IMEX-linearised KNP-EMI step (eq. ``lin_sys``).
+//
+// Every kernel is a deterministic gather: one thread owns one region vertex
+// (one scalar row, i.e. four global rows) and walks the elements or membrane
+// facets incident to it in a fixed order, accumulating into LDS slots indexed
+// by the row's column positions.  No floating-point atomics are used, so two
+// runs are bitwise identical.
+//
+// Integrals are exact for P1: on a simplex of dimension m with measure |T|,
+//   int prod lambda_a^{p_a} = m! |T| prod p_a! / (m + sum p_a)!.
+#include <hip/hip_runtime.h>
+
+#include "knp_internal.h"
+
+namespace knp {
+namespace launch {
+
+namespace {
+
+constexpr int BLK = 64;   // one wavefront per block; LDS slots are [..][pos][thread]
+
+// Volume and barycentric gradients of a simplex with vertices x[a] (D = 2 or 3).
+template <int D>
+__device__ inline double simplex_grads(const double (&x)[D + 1][D], double (&g)[D + 1][D]) {
+    double J[D][D];   // J[r][c] = x[c+1][r] - x[0][r]
+#pragma unroll
+    for (int c = 0; c < D; ++c)
+#pragma unroll
+        for (int r = 0; r < D; ++r) J[r][c] = x[c + 1][r] - x[0][r];
+    double det, inv[D][D];
+    if constexpr (D == 2) {
+        det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+        inv[0][0] = J[1][1] / det;
+        inv[0][1] = -J[0][1] / det;
+        inv[1][0] = -J[1][0] / det;
+        inv[1][1] = J[0][0] / det;
+    } else {
+        const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+        const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+        const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+        det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+        inv[0][0] = c00 / det;
+        inv[1][0] = c01 / det;
+        inv[2][0] = c02 / det;
+        inv[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
+        inv[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det;
+        inv[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det;
+        inv[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det;
+        inv[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det;
+        inv[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
+    }
+    // rows of J^{-1} are grad(lambda_1..D); grad(lambda_0) = -sum
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        double s = 0.0;
+#pragma unroll
+        for (int a = 1; a <= D; ++a) {
+            g[a][d] = inv[a - 1][d];
+            s += inv[a - 1][d];
+        }
+        g[0][d] = -s;
+    }
+    const double fact = (D == 2) ? 2.0 : 6.0;
+    return fabs(det) / fact;
+}
+
+template <int D>
+__device__ inline void load_simplex(const MeshArgs &ma, int32_t e, int32_t (&vg)[D + 1], double (&x)[D + 1][D]) {
+#pragma unroll
+    for (int a = 0; a <= D; ++a) {
+        vg[a] = ma.elem[int64_t(e) * (D + 1) + a];
+#pragma unroll
+        for (int d = 0; d < D; ++d) x[a][d] = ma.xyz[int64_t(vg[a]) * D + d];
+    }
+}
+
+// int over a D-simplex of lambda_a lambda_b, divided by |T|
+template <int D>
+__device__ inline double mass_moment(bool same) {
+    return (same ? 2.0 : 1.0) / double((D + 1) * (D + 2));
+}
+
+// facet (dimension m = D-1) moments divided by |F|
+template <int D>
+__device__ inline double fmom2(int a, int b) {
+    constexpr int m = D - 1;
+    constexpr double base = (m == 1) ? 1.0 / 6.0 : 1.0 / 12.0;   // m!/(m+2)!
+    return (a == b ? 2.0 : 1.0) * base;
+}
+template <int D>
+__device__ inline double fmom3(int a, int b, int c) {
+    constexpr int m = D - 1;
+    constexpr double base = (m == 1) ? 1.0 / 24.0 : 1.0 / 60.0;  // m!/(m+3)!
+    const int eq = (a == b) + (a == c) + (b == c);
+    const double mult = eq == 3 ? 6.0 : (eq == 1 ? 2.0 : 1.0);
+    return mult * base;
+}
+
+template <int D>
+__device__ inline double facet_measure(const MeshArgs &ma, const int32_t *fv) {
+    double x[D][D];
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int d = 0; d < D; ++d) x[a][d] = ma.xyz[int64_t(fv[a]) * D + d];
+    if constexpr (D == 2) {
+        const double dx = x[1][0] - x[0][0], dy = x[1][1] - x[0][1];
+        return sqrt(dx * dx + dy * dy);
+    } else {
+        const double ax = x[1][0] - x[0][0], ay = x[1][1] - x[0][1], az = x[1][2] - x[0][2];
+        const double bx = x[2][0] - x[0][0], by = x[2][1] - x[0][1], bz = x[2][2] - x[0][2];
+        const double cx = ay * bz - az * by, cy = az * bx - ax * bz, cz = ax * by - ay * bx;
+        return 0.5 * sqrt(cx * cx + cy * cy + cz * cz);
+    }
+}
+
+// ------------------------------------------------------------------ membrane coefficients
+// Hodgkin-Huxley 1952 rates in 1/s; V in mV relative to rest.
+__device__ inline double hh_ratio(double x) {   // x / (exp(x/10) - 1), limit 10
+    return x == 0.0 ? 10.0 : x / expm1(x / 10.0);
+}
+
+__device__ inline void hh_rates(double V, double (&a)[3], double (&b)[3]) {
+    a[0] = 0.01 * hh_ratio(10.0 - V) * 1000.0;
+    b[0] = 0.125 * exp(-V / 80.0) * 1000.0;
+    a[1] = 0.1 * hh_ratio(25.0 - V) * 1000.0;
+    b[1] = 4.0 * exp(-V / 18.0) * 1000.0;
+    a[2] = 0.07 * exp(-V / 20.0) * 1000.0;
+    b[2] = 1.0 / (exp((30.0 - V) / 10.0) + 1.0) * 1000.0;
+}
+
+__global__ void k_membrane_coef(GammaArgs g, PhysArgs p, int64_t Ni, int64_t Ne, const double *__restrict__ u,
+                                double *__restrict__ gates, const double *__restrict__ theta,
+                                double *__restrict__ gc) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= g.n_gamma) return;
+    const int64_t li = g.gloc_i[i], le = g.gloc_e[i];
+    const int cell = g.gcell[i] - 1;
+    const int64_t offe = 4 * Ni;
+    double ci[3], ce[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        ci[k] = u[k * Ni + li];
+        ce[k] = u[offe + k * Ne + le];
+    }
+    const double phiM = u[3 * Ni + li] - u[offe + 3 * Ne + le];
+    const int model = g.cell_model[cell];
+    const int stim = g.cell_stim[cell];
+    const double th = theta ? theta[cell] : 1.0;
+
+    double gk[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) gk[k] = th * p.g_leak[k];
+    if (stim) gk[0] += p.g_stim_bar * exp(-fmod(p.t, p.stim_tau) / p.stim_a);
+    if (model == 1) {
+        // n_ode Rush-Larsen sub-steps of the gating ODE with phi_M frozen at phi_M^{n-1}
+        double w[3] = {gates[3 * i + 0], gates[3 * i + 1], gates[3 * i + 2]};
+        double a[3], b[3];
+        hh_rates(1000.0 * (phiM - p.phi_rest), a, b);
+        const double hs = p.dt / p.n_ode;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const double tinv = a[q] + b[q];
+            const double winf = a[q] / tinv;
+            const double decay = exp(-tinv * hs);
+            for (int s = 0; s < p.n_ode; ++s) w[q] = winf + (w[q] - winf) * decay;
+            gates[3 * i + q] = w[q];
+        }
+        gk[0] += p.gbar_Na * w[1] * w[1] * w[1] * w[2];
+        gk[1] += p.gbar_K * w[0] * w[0] * w[0] * w[0];
+    }
+    double I[3], Itot = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double E = p.psi / p.z[k] * log(ce[k] / ci[k]);
+        I[k] = gk[k] * (phiM - E);
+        Itot += I[k];
+    }
+    double *o = gc + i * GC_STRIDE;
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const double *c = r == 0 ? ci : ce;
+        const double sgn = r == 0 ? 1.0 : -1.0;
+        double wsum = 0.0, wk[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            wk[k] = p.D[k] * p.z[k] * p.z[k] * c[k];
+            wsum += wk[k];
+        }
+        double *orr = o + r * GC_REGION;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const double alpha = wk[k] / wsum;
+            orr[GC_C + k] = alpha * p.C_m / (p.F * p.z[k]);
+            orr[GC_G + k] = sgn * (p.dt * I[k] - alpha * p.C_m * phiM) / (p.F * p.z[k]);
+        }
+        orr[GC_H] = sgn * (p.dt * Itot - p.C_m * phiM) / p.F;
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) o[GC_I + k] = I[k];
+}
+
+// ------------------------------------------------------------------ bulk, static part
+// c_r^k rows, own block: M + tau_k A;  phi_r row, c_r^k blocks: z_k tau_k A.
+template <int D>
+__global__ void __launch_bounds__(BLK) k_static(RegionArgs ra, MeshArgs ma, PhysArgs p,
+                                                const int64_t *__restrict__ rowptr, double *__restrict__ vals,
+                                                const double *__restrict__ sc, int64_t pin_dof) {
+    __shared__ double sA[MAXN][BLK];
+    __shared__ double sM[MAXN][BLK];
+    const int tid = threadIdx.x;
+    const int64_t j = int64_t(blockIdx.x) * BLK + tid;
+    if (j >= ra.Nr) return;
+    const int64_t p0 = ra.prow[j];
+    const int n = int(ra.prow[j + 1] - p0);
+    for (int q = 0; q < n; ++q) {
+        sA[q][tid] = 0.0;
+        sM[q][tid] = 0.0;
+    }
+    const int32_t *loc = ra.r == 0 ? ma.loc_i : ma.loc_e;
+    for (int64_t t = ra.irow[j]; t < ra.irow[j + 1]; ++t) {
+        const int32_t e = ra.ielem[t];
+        const uint32_t pk = ra.ipos[t];
+        const int slot = pk & 3u;
+        int32_t vg[D + 1];
+        double x[D + 1][D], g[D + 1][D];
+        load_simplex<D>(ma, e, vg, x);
+        const double vol = simplex_grads<D>(x, g);
+#pragma unroll
+        for (int a = 0; a <= D; ++a) {
+            const int q = (pk >> (2 + 5 * a)) & 31u;
+            double dot = 0.0;
+#pragma unroll
+            for (int d = 0; d < D; ++d) dot += g[slot][d] * g[a][d];
+            sA[q][tid] += vol * dot;
+            sM[q][tid] += vol * mass_moment<D>(a == slot);
+        }
+    }
+    (void)loc;
+    const int64_t Nr = ra.Nr;
+    const int32_t *pc = ra.pcol + p0;
+    for (int k = 0; k < 3; ++k) {
+        const int64_t row = ra.off + k * Nr + j;
+        const int64_t rp = rowptr[row];
+        const int gq = int(rowptr[row + 1] - rp) - 2 * n;
+        const int64_t seg = rp + (ra.r == 0 ? 0 : gq);
+        const double sr = sc[row];
+        for (int q = 0; q < n; ++q) {
+            const int64_t col = ra.off + k * Nr + pc[q];
+            vals[seg + q] = (sM[q][tid] + p.tau[k] * sA[q][tid]) * sr * sc[col];
+        }
+    }
+    const int64_t row = ra.off + 3 * Nr + j;
+    const int64_t rp = rowptr[row];
+    const int gq = int(rowptr[row + 1] - rp) - 4 * n;
+    const int64_t seg0 = rp + (ra.r == 0 ? 0 : gq);
+    const double sr = sc[row];
+    const bool pinrow = row == pin_dof;
+    for (int k = 0; k < 3; ++k)
+        for (int q = 0; q < n; ++q) {
+            const int64_t col = ra.off + k * Nr + pc[q];
+            vals[seg0 + k * n + q] = pinrow ? 0.0 : p.z[k] * p.tau[k] * sA[q][tid] * sr * sc[col];
+        }
+}
+
+// ------------------------------------------------------------------ bulk, per-step part
+// c_r^k rows, phi_r block: tilde-tau_k A_r^k;  phi_r row, phi_r block:
+// sum_k z_k tilde-tau_k A_r^k;  RHS f_r^k = M_r c^{k,n-1}, f_r^phi = 0.
+// A_r^k uses c^{k,n-1} (exact for P1: element mean times the element stiffness).
+template <int D>
+__global__ void __launch_bounds__(BLK) k_dynamic(RegionArgs ra, MeshArgs ma, PhysArgs p,
+                                                 const int64_t *__restrict__ rowptr, double *__restrict__ vals,
+                                                 const double *__restrict__ sc, const double *__restrict__ u,
+                                                 double *__restrict__ f, int64_t pin_dof) {
+    __shared__ double sK[3][MAXN][BLK];
+    const int tid = threadIdx.x;
+    const int64_t j = int64_t(blockIdx.x) * BLK + tid;
+    if (j >= ra.Nr) return;
+    const int64_t p0 = ra.prow[j];
+    const int n = int(ra.prow[j + 1] - p0);
+    for (int q = 0; q < n; ++q) sK[0][q][tid] = sK[1][q][tid] = sK[2][q][tid] = 0.0;
+    const int32_t *loc = ra.r == 0 ? ma.loc_i : ma.loc_e;
+    const int64_t Nr = ra.Nr;
+    const double *cb = u + ra.off;
+    double mc[3] = {0.0, 0.0, 0.0};
+    for (int64_t t = ra.irow[j]; t < ra.irow[j + 1]; ++t) {
+        const int32_t e = ra.ielem[t];
+        const uint32_t pk = ra.ipos[t];
+        const int slot = pk & 3u;
+        int32_t vg[D + 1];
+        double x[D + 1][D], g[D + 1][D];
+        load_simplex<D>(ma, e, vg, x);
+        const double vol = simplex_grads<D>(x, g);
+        double cv[3][D + 1], cbar[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int a = 0; a <= D; ++a) {
+            const int64_t l = loc[vg[a]];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                cv[k][a] = cb[k * Nr + l];
+                cbar[k] += cv[k][a];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) cbar[k] /= double(D + 1);
+#pragma unroll
+        for (int a = 0; a <= D; ++a) {
+            const int q = (pk >> (2 + 5 * a)) & 31u;
+            double dot = 0.0;
+#pragma unroll
+            for (int d = 0; d < D; ++d) dot += g[slot][d] * g[a][d];
+            const double K = vol * dot;
+            const double Mv = vol * mass_moment<D>(a == slot);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                sK[k][q][tid] += cbar[k] * K;
+                mc[k] += Mv * cv[k][a];
+            }
+        }
+    }
+    const int32_t *pc = ra.pcol + p0;
+    const int64_t phib = ra.off + 3 * Nr;
+    for (int k = 0; k < 3; ++k) {
+        const int64_t row = ra.off + k * Nr + j;
+        const int64_t rp = rowptr[row];
+        const int gq = int(rowptr[row + 1] - rp) - 2 * n;
+        const int64_t seg = rp + (ra.r == 0 ? 0 : gq) + n;
+        const double sr = sc[row];
+        for (int q = 0; q < n; ++q) {
+            const int64_t col = phib + pc[q];
+            const double v = p.ttau[k] * sK[k][q][tid];
+            vals[seg + q] = col == pin_dof ? 0.0 : v * sr * sc[col];
+        }
+        f[row] = mc[k];
+    }
+    const int64_t row = phib + j;
+    const int64_t rp = rowptr[row];
+    const int gq = int(rowptr[row + 1] - rp) - 4 * n;
+    const int64_t seg = rp + (ra.r == 0 ? 0 : gq) + 3 * n;
+    const double sr = sc[row];
+    const bool pinrow = row == pin_dof;
+    for (int q = 0; q < n; ++q) {
+        const int64_t col = phib + pc[q];
+        double v = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) v += p.z[k] * p.ttau[k] * sK[k][q][tid];
+        const bool keep = pinrow ? (col == row) : (col != pin_dof);
+        vals[seg + q] = keep ? v * sr * sc[col] : 0.0;
+    }
+    f[row] = 0.0;
+}
+
+// ------------------------------------------------------------------ membrane part
+// For a membrane vertex a in region r (sgn_r = +1 for ICS, -1 for ECS), with the
+// P1 membrane fields C_r^k, g_r^k, h_r:
+//   c_r^k row: phi_r block += int C_r^k phi_a phi_b,  phi_q block = -int C_r^k phi_a phi_b
+//   phi_r row: phi_r block += C_m/F int phi_a phi_b,  phi_q block = -C_m/F int phi_a phi_b
+//   f_r^k -= int g_r^k phi_a,  f_r^phi -= int h_r phi_a.
+constexpr int MBLK = 32;
+
+template <int D>
+__global__ void __launch_bounds__(MBLK) k_membrane(GammaArgs g, MeshArgs ma, PhysArgs p, int64_t Ni, int64_t Ne,
+                                                   const int64_t *__restrict__ prow_i,
+                                                   const int64_t *__restrict__ prow_e,
+                                                   const int64_t *__restrict__ rowptr, double *__restrict__ vals,
+                                                   const int32_t *__restrict__ colidx,
+                                                   const double *__restrict__ sc, const double *__restrict__ gc,
+                                                   double *__restrict__ f) {
+    __shared__ double sC[3][MAXN][MBLK];
+    __shared__ double sS[MAXN][MBLK];
+    __shared__ double sX[3][MAXG][MBLK];
+    __shared__ double sXS[MAXG][MBLK];
+    const int tid = threadIdx.x;
+    const int64_t it = int64_t(blockIdx.x) * MBLK + tid;
+    if (it >= 2 * g.n_gamma) return;
+    const int r = int(it & 1);
+    const int64_t gi = it >> 1;
+    const int64_t Nr = r == 0 ? Ni : Ne, Nq = r == 0 ? Ne : Ni;
+    const int64_t offr = r == 0 ? 0 : 4 * Ni, offq = r == 0 ? 4 * Ni : 0;
+    const int64_t j = r == 0 ? g.gloc_i[gi] : g.gloc_e[gi];
+    const int64_t *prow = r == 0 ? prow_i : prow_e;
+    const int n = int(prow[j + 1] - prow[j]);
+    const uint32_t *fpos = r == 0 ? g.fpos_i : g.fpos_e;
+    const int64_t row0 = offr + j;
+    (void)Nq;
+    const int gn = int(rowptr[row0 + 1] - rowptr[row0]) - 2 * n;
+    for (int q = 0; q < n; ++q) {
+        sC[0][q][tid] = sC[1][q][tid] = sC[2][q][tid] = 0.0;
+        sS[q][tid] = 0.0;
+    }
+    for (int q = 0; q < gn; ++q) {
+        sX[0][q][tid] = sX[1][q][tid] = sX[2][q][tid] = 0.0;
+        sXS[q][tid] = 0.0;
+    }
+    double fg[4] = {0.0, 0.0, 0.0, 0.0};
+    const double cmf = p.C_m / p.F;
+    for (int64_t t = g.frow[gi]; t < g.frow[gi + 1]; ++t) {
+        const int32_t *fv = g.facets + int64_t(g.ffacet[t]) * D;
+        const uint32_t pk = fpos[t];
+        const int slot = pk & 3u;
+        const double meas = facet_measure<D>(ma, fv);
+        double Cv[3][D], gv[3][D], hv[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            const double *c = gc + int64_t(g.gidx[fv[a]]) * GC_STRIDE + r * GC_REGION;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                Cv[k][a] = c[GC_C + k];
+                gv[k][a] = c[GC_G + k];
+            }
+            hv[a] = c[GC_H];
+        }
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            const int qr = (pk >> (2 + 5 * a)) & 31u;
+            const int qg = (pk >> (17 + 4 * a)) & 15u;
+            const double m2 = meas * fmom2<D>(slot, a);
+            sS[qr][tid] += cmf * m2;
+            sXS[qg][tid] -= cmf * m2;
+            fg[3] -= hv[a] * m2;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                fg[k] -= gv[k][a] * m2;
+                double w = 0.0;
+#pragma unroll
+                for (int c = 0; c < D; ++c) w += Cv[k][c] * fmom3<D>(slot, a, c);
+                w *= meas;
+                sC[k][qr][tid] += w;
+                sX[k][qg][tid] -= w;
+            }
+        }
+    }
+    // write: phi_r block adds to the bulk values of this row (this thread owns it);
+    // phi_q block (membrane neighbours, ascending) is written outright
+    for (int k = 0; k < 4; ++k) {
+        const int64_t row = offr + k * Nr + j;
+        const int64_t rp = rowptr[row];
+        const int nb = k < 3 ? 1 : 3;              // blocks preceding phi_r in this row
+        const int64_t seg_phi = rp + (r == 0 ? 0 : gn) + int64_t(nb) * n;
+        const int64_t seg_q = r == 0 ? rp + int64_t(nb + 1) * n : rp;
+        const double sr = sc[row];
+        for (int q = 0; q < n; ++q) {
+            const int64_t pos = seg_phi + q;
+            const double add = k < 3 ? sC[k][q][tid] : sS[q][tid];
+            vals[pos] += add * sr * sc[colidx[pos]];
+        }
+        for (int q = 0; q < gn; ++q) {
+            const int64_t pos = seg_q + q;
+            const double v = k < 3 ? sX[k][q][tid] : sXS[q][tid];
+            vals[pos] = v * sr * sc[colidx[pos]];
+        }
+        f[row] += fg[k];
+    }
+    (void)Nq;
+    (void)offq;
+}
+
+// ------------------------------------------------------------------ helpers
+__global__ void k_check_finite(const double *__restrict__ u, int64_t n, int *flag) {
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+        if (!isfinite(u[i])) *flag = 1;
+}
+
+__global__ void k_rescale(int64_t N, const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+                          double *__restrict__ vals, const double *__restrict__ sc) {
+    const int64_t row = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (row >= N) return;
+    const double sr = sc[row];
+    for (int64_t k = rowptr[row]; k < rowptr[row + 1]; ++k) vals[k] *= sr * sc[col[k]];
+}
+
+__global__ void k_scaling_from_diag(int64_t N, const double *__restrict__ vals, const int64_t *__restrict__ dpos,
+                                    double *__restrict__ sc) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const double d = fabs(vals[dpos[i]]);
+    sc[i] = d > 0.0 ? 1.0 / sqrt(d) : 1.0;
+}
+
+__global__ void k_gather(int64_t n, const double *__restrict__ src, const int64_t *__restrict__ map,
+                         double *__restrict__ dst) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[map[i]];
+}
+
+__global__ void k_scale_vec(int64_t n, const double *__restrict__ x, const double *__restrict__ sc,
+                            double *__restrict__ y, int invert) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = invert ? x[i] / sc[i] : x[i] * sc[i];
+}
+
+inline unsigned nblocks(int64_t n, int b) { return unsigned((n + b - 1) / b); }
+
+}  // namespace
+
+void check_finite(const double *u, int64_t n, int *flag, hipStream_t s) {
+    hipLaunchKernelGGL(k_check_finite, dim3(1024), dim3(256), 0, s, u, n, flag);
+}
+
+void membrane_coefficients(const GammaArgs &g, const PhysArgs &p, int64_t Ni, int64_t Ne, const double *u_prev,
+                           double *gates, const double *theta, double *gcoef, hipStream_t s) {
+    if (g.n_gamma == 0) return;
+    hipLaunchKernelGGL(k_membrane_coef, dim3(nblocks(g.n_gamma, 128)), dim3(128), 0, s, g, p, Ni, Ne, u_prev,
+                       gates, theta, gcoef);
+}
+
+void assemble_static(const RegionArgs &ra, const MeshArgs &ma, const PhysArgs &p, const int64_t *rowptr,
+                     double *vals, const double *sc, int64_t pin_dof, hipStream_t s) {
+    if (ra.Nr == 0) return;
+    if (ma.dim == 2)
+        hipLaunchKernelGGL(k_static<2>, dim3(nblocks(ra.Nr, BLK)), dim3(BLK), 0, s, ra, ma, p, rowptr, vals, sc,
+                           pin_dof);
+    else
+        hipLaunchKernelGGL(k_static<3>, dim3(nblocks(ra.Nr, BLK)), dim3(BLK), 0, s, ra, ma, p, rowptr, vals, sc,
+                           pin_dof);
+}
+
+void assemble_dynamic(const RegionArgs &ra, const MeshArgs &ma, const PhysArgs &p, const int64_t *rowptr,
+                      double *vals, const double *sc, const double *u_prev, double *f, int64_t pin_dof,
+                      hipStream_t s) {
+    if (ra.Nr == 0) return;
+    if (ma.dim == 2)
+        hipLaunchKernelGGL(k_dynamic<2>, dim3(nblocks(ra.Nr, BLK)), dim3(BLK), 0, s, ra, ma, p, rowptr, vals, sc,
+                           u_prev, f, pin_dof);
+    else
+        hipLaunchKernelGGL(k_dynamic<3>, dim3(nblocks(ra.Nr, BLK)), dim3(BLK), 0, s, ra, ma, p, rowptr, vals, sc,
+                           u_prev, f, pin_dof);
+}
+
+void assemble_membrane(const GammaArgs &g, const MeshArgs &ma, const PhysArgs &p, int64_t Ni, int64_t Ne,
+                       const int64_t *prow_i, const int64_t *prow_e, const int64_t *rowptr, const int32_t *colidx,
+                       double *vals, const double *sc, const double *gcoef, double *f, hipStream_t s) {
+    if (g.n_gamma == 0) return;
+    const unsigned nb = nblocks(2 * g.n_gamma, MBLK);
+    if (ma.dim == 2)
+        hipLaunchKernelGGL(k_membrane<2>, dim3(nb), dim3(MBLK), 0, s, g, ma, p, Ni, Ne, prow_i, prow_e, rowptr,
+                           vals, colidx, sc, gcoef, f);
+    else
+        hipLaunchKernelGGL(k_membrane<3>, dim3(nb), dim3(MBLK), 0, s, g, ma, p, Ni, Ne, prow_i, prow_e, rowptr,
+                           vals, colidx, sc, gcoef, f);
+}
+
+void rescale_system(int64_t N, const int64_t *rowptr, const int32_t *col, double *vals, const double *sc,
+                    hipStream_t s) {
+    hipLaunchKernelGGL(k_rescale, dim3(nblocks(N, 256)), dim3(256), 0, s, N, rowptr, col, vals, sc);
+}
+
+void scaling_from_diag(int64_t N, const double *vals, const int64_t *diag_pos, double *sc, hipStream_t s) {
+    hipLaunchKernelGGL(k_scaling_from_diag, dim3(nblocks(N, 256)), dim3(256), 0, s, N, vals, diag_pos, sc);
+}
+
+void gather(int64_t n, const double *src, const int64_t *map, double *dst, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_gather, dim3(nblocks(n, 256)), dim3(256), 0, s, n, src, map, dst);
+}
+
+void scale_vec(int64_t n, const double *x, const double *sc, double *y, int invert, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_scale_vec, dim3(nblocks(n, 256)), dim3(256), 0, s, n, x, sc, y, invert);
+}
+
+}  // namespace launch
+}  // namespace knp

@@ -1,0 +1,73 @@
+// The opaque context behind knp_ctx: mesh, device-resident system, AMG
+// hierarchy and Krylov workspace of one HIP device and stream.
+#pragma once
+
+#include "knp_internal.h"
+
+struct knp_ctx {
+    int device = -1;
+    bool host_only = true;
+    hipStream_t stream = nullptr;
+    std::string err;
+
+    bool have_mesh = false, have_params = false, assembled = false;
+
+    knp::HostMesh hm;
+
+    // parameters
+    knp_params prm{};
+    std::vector<int32_t> cell_model, cell_stim;
+    bool any_hh = false;
+
+    // device mesh data
+    knp::DArray<double> d_xyz;
+    knp::DArray<int32_t> d_elem, d_loc[2], d_verts[2];
+    knp::DArray<int64_t> d_prow[2], d_irow[2];
+    knp::DArray<int32_t> d_pcol[2], d_ielem[2];
+    knp::DArray<uint32_t> d_ipos[2];
+    knp::DArray<int32_t> d_gamma, d_gloc_i, d_gloc_e, d_gcell, d_ffacet, d_facets, d_gidx;
+    knp::DArray<int64_t> d_frow;
+    knp::DArray<uint32_t> d_fpos[2];
+    knp::DArray<int32_t> d_cell_model, d_cell_stim;
+    knp::DArray<double> d_gcoef;
+
+    // system
+    knp::DArray<int64_t> d_rowptr, d_diag;
+    knp::DArray<int32_t> d_colidx;
+    knp::DArray<double> d_vals, d_sc;
+    knp::DArray<int32_t> d_flag;
+    double dt_static = -1.0;
+    double dt_first = -1.0;
+
+    // transposed system (adjoint)
+    bool have_T = false, T_current = false;
+    knp::DArray<int64_t> d_rowptrT, d_permT;
+    knp::DArray<int32_t> d_colT;
+    knp::DArray<double> d_valsT;
+
+    // preconditioner
+    std::vector<double> p0_vals, near_null;
+    knp::Amg amg;
+
+    knp::Timers tm;
+    double assembly_bytes = 0.0;
+
+    // Krylov workspace
+    int m_alloc = -1;
+    bool z32 = false;
+    knp::DArray<double> V, Z64, w, bh, yh, partial, dscal;
+    knp::DArray<float> Z32;
+    int nblk = 1;
+
+    knp::launch::RegionArgs region(int r) const;
+    knp::launch::MeshArgs mesh_args() const;
+    knp::launch::GammaArgs gamma_args() const;
+    knp::launch::PhysArgs phys(double t, double dt) const;
+};
+
+namespace knp {
+knp_status krylov_solve(knp_ctx *c, bool transpose, const double *b, double *x, const knp_solve_opts &o,
+                        knp_solve_info *info);
+void ensure_transpose(knp_ctx *c);
+void apply_operator(knp_ctx *c, bool transpose, const double *x, double *y);
+}  // namespace knp

@@ -1,0 +1,280 @@
+// Internal declarations of libknp: host mesh structures, device buffers,
+// AMG hierarchy, solver workspace and the kernel launchers shared between
+// the host C++ translation units and the HIP kernel translation units.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/knp.h"
+
+namespace knp {
+
+// Kernel limits for the per-row gather assembly.
+constexpr int MAXN = 32;   // scalar neighbours (incl. self) of a vertex in one region
+constexpr int MAXG = 16;   // membrane neighbours (incl. self) of a membrane vertex
+
+// Layout of the per-membrane-vertex coefficient record written by the membrane
+// kernel: for r in {i, e}: C_r^k (3), g_r^k (3), h_r (1); then I_ch^k (3).
+constexpr int GC_STRIDE = 20;
+constexpr int GC_C = 0, GC_G = 3, GC_H = 6, GC_REGION = 7, GC_I = 14;
+
+struct Error {
+    knp_status st;
+    std::string msg;
+};
+
+// ----------------------------------------------------------------------------- host mesh
+struct HostMesh {
+    int dim = 0;
+    int64_t n_vert = 0, n_elem = 0;
+    std::vector<double> xyz;        // [n_vert*dim]
+    std::vector<int32_t> elem;      // [n_elem*(dim+1)]
+    std::vector<int32_t> tag;       // [n_elem]
+    int32_t n_cells = 0;
+    int64_t Nr[2] = {0, 0};
+    int64_t off[2] = {0, 0};
+    std::vector<int32_t> loc[2];    // [n_vert] region-local index or -1
+    std::vector<int32_t> verts[2];  // region vertices (global ids, ascending)
+    std::vector<int32_t> vcell;     // [n_vert] cell id of ICS vertices, 0 otherwise
+    std::vector<int32_t> gamma;     // membrane vertices, ascending
+    std::vector<int32_t> gidx;      // [n_vert] index into gamma or -1
+    std::vector<int32_t> facets;    // [n_f*dim] membrane facets (global ids, ascending per facet)
+    int64_t n_facets = 0;
+    // scalar pattern of each region (region-local indices, ascending)
+    std::vector<int64_t> prow[2];
+    std::vector<int32_t> pcol[2];
+    // membrane adjacency: per membrane vertex, neighbour global ids (ascending)
+    std::vector<int64_t> grow;
+    std::vector<int32_t> gcol;
+    // element incidence per region vertex; ipos packs the slot of the row vertex
+    // in the element (bits 0-1) and the row positions of the element's vertices
+    // (5 bits each from bit 2)
+    std::vector<int64_t> irow[2];
+    std::vector<int32_t> ielem[2];
+    std::vector<uint32_t> ipos[2];
+    // facet incidence per membrane vertex; fpos[r] packs the slot of the row vertex
+    // (bits 0-1), the region-r row positions (5 bits each from bit 2) and the
+    // membrane-row positions (4 bits each from bit 17)
+    std::vector<int64_t> frow;
+    std::vector<int32_t> ffacet;
+    std::vector<uint32_t> fpos[2];
+    // global CSR pattern
+    int64_t N = 0, nnz = 0, nnz_p0 = 0;
+    std::vector<int64_t> rowptr;
+    std::vector<int32_t> colidx;
+    std::vector<int64_t> diag_pos;  // [N]
+    int64_t pin_vertex = 0, pin_dof = 0;
+};
+
+// Builds everything above from the raw mesh; throws Error.
+void build_host_mesh(HostMesh &m, int dim, int64_t n_vert, const double *xyz, int64_t n_elem,
+                     const int32_t *elem, const int32_t *tag, int64_t pin_vertex);
+
+// ----------------------------------------------------------------------------- device buffer
+template <typename T>
+struct DArray {
+    T *p = nullptr;
+    size_t n = 0;
+    DArray() = default;
+    DArray(const DArray &) = delete;
+    DArray &operator=(const DArray &) = delete;
+    ~DArray() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    void alloc(size_t count);                  // throws Error on failure
+    void upload(const T *h, size_t count, hipStream_t s);
+    void upload(const std::vector<T> &v, hipStream_t s) { upload(v.data(), v.size(), s); }
+    void download(T *h, size_t count, hipStream_t s) const;
+};
+
+void hip_check(hipError_t e, const char *what);   // throws Error(KNP_E_HIP)
+
+// ----------------------------------------------------------------------------- timing
+// Event-bracketed launches per kernel class; elapsed times are harvested at the
+// next host synchronisation point.
+struct Timers {
+    bool on = false;
+    struct Cls {
+        std::vector<hipEvent_t> a, b;   // pending start/stop pairs
+        std::vector<double> bytes;      // pending algorithmic bytes
+        int64_t launches = 0;
+        double ms = 0.0, total_bytes = 0.0;
+    } cls[KNP_TIMER_COUNT];
+    std::vector<hipEvent_t> pool;
+    hipEvent_t begin(int k, hipStream_t s);
+    void end(int k, hipEvent_t start, double bytes, hipStream_t s);
+    void harvest();   // call after the stream has been synchronised
+    void reset();
+    ~Timers();
+};
+
+// ----------------------------------------------------------------------------- AMG
+struct Csr {
+    int64_t nrows = 0, ncols = 0;
+    std::vector<int64_t> rowptr;
+    std::vector<int32_t> col;
+    std::vector<double> val;
+    int64_t nnz() const { return rowptr.empty() ? 0 : rowptr.back(); }
+};
+
+struct DevCsr {
+    int64_t nrows = 0, ncols = 0, nnz = 0;
+    DArray<int64_t> rowptr;
+    DArray<int32_t> col;
+    DArray<double> val64;
+    DArray<float> val32;
+    void upload(const Csr &h, bool fp32, hipStream_t s);
+};
+
+struct Level {
+    int64_t n = 0;
+    double lmax = 2.0;           // spectral radius estimate of the (unit-diagonal) operator
+    DevCsr A, P, R;              // P: n x n_coarse, R = P^T
+    // level vectors (precision of the hierarchy); x2 is the Chebyshev ping-pong buffer
+    DArray<double> b64, x64, x2_64, t64, d64;
+    DArray<float> b32, x32, x2_32, t32, d32;
+};
+
+struct Amg {
+    bool ready = false;
+    bool fp32 = false;
+    int degree = 2;
+    double ratio = 10.0;
+    std::vector<Level *> levels;     // levels[0] is P_0
+    // coarsest-level dense inverses, one per connected component
+    int64_t n_coarse = 0;
+    DArray<int32_t> ccomp;           // [n_coarse] component of each coarsest row
+    DArray<int32_t> cloc;            // [n_coarse] position of the row inside its component
+    DArray<int32_t> cmem;            // [n_coarse] rows of each component, concatenated
+    DArray<int64_t> cstart;          // [n_blocks+1] start of each component in cmem
+    DArray<int64_t> coff;            // [n_blocks] offset of the component's inverse
+    DArray<double> cinv;             // packed dense inverses (row-major)
+    DArray<double> cb64, cx64;       // coarse rhs / solution in FP64
+    int64_t n_blocks = 0;
+    std::vector<int64_t> level_nnz, level_n;
+    ~Amg();
+    void clear();
+};
+
+void amg_build(Amg &amg, const HostMesh &m, const std::vector<double> &p0_vals,
+               const std::vector<double> &near_null, const knp_amg_opts &o, hipStream_t s);
+// z = V-cycle(v) on level 0; v is FP64; z is FP64 or FP32 per amg.fp32
+void amg_vcycle(Amg &amg, const double *v, void *z, hipStream_t s, Timers *tm = nullptr);
+
+}  // namespace knp
+
+// ----------------------------------------------------------------------------- kernel launchers
+namespace knp {
+namespace launch {
+
+struct RegionArgs {
+    int r;                     // 0 = ICS, 1 = ECS
+    int dim;
+    int64_t Nr, off, off_q;    // region size, DOF offsets of this and the other region
+    int64_t Nq;
+    const int64_t *prow;       // scalar pattern row pointers
+    const int32_t *pcol;
+    const int64_t *irow;       // element incidence
+    const int32_t *ielem;
+    const uint32_t *ipos;
+    const int32_t *verts;      // region vertices (global)
+};
+
+struct MeshArgs {
+    int dim;
+    const double *xyz;
+    const int32_t *elem;
+    const int32_t *loc_i, *loc_e;
+};
+
+struct PhysArgs {
+    double z[3], D[3], tau[3], ttau[3];
+    double F, C_m, psi, dt, t;
+    double g_leak[3], gbar_Na, gbar_K, g_stim_bar, stim_a, stim_tau, phi_rest;
+    int n_ode;
+};
+
+struct GammaArgs {
+    int64_t n_gamma;
+    const int32_t *gamma;      // global ids
+    const int32_t *gloc_i, *gloc_e, *gcell;   // local indices and cell (1-based)
+    const int64_t *frow;
+    const int32_t *ffacet;
+    const uint32_t *fpos_i, *fpos_e;
+    const int32_t *facets;
+    const int32_t *gidx;       // [n_vert]
+    const int32_t *cell_model, *cell_stim;
+};
+
+void check_finite(const double *u, int64_t n, int *flag, hipStream_t s);
+void membrane_coefficients(const GammaArgs &g, const PhysArgs &p, int64_t Ni, int64_t Ne, const double *u_prev,
+                           double *gates, const double *theta, double *gcoef, hipStream_t s);
+void assemble_static(const RegionArgs &ra, const MeshArgs &ma, const PhysArgs &p,
+                     const int64_t *rowptr, double *vals, const double *sc, int64_t pin_dof,
+                     hipStream_t s);
+void assemble_dynamic(const RegionArgs &ra, const MeshArgs &ma, const PhysArgs &p,
+                      const int64_t *rowptr, double *vals, const double *sc, const double *u_prev,
+                      double *f, int64_t pin_dof, hipStream_t s);
+void assemble_membrane(const GammaArgs &g, const MeshArgs &ma, const PhysArgs &p, int64_t Ni, int64_t Ne,
+                       const int64_t *prow_i, const int64_t *prow_e, const int64_t *rowptr, const int32_t *colidx,
+                       double *vals, const double *sc, const double *gcoef, double *f, hipStream_t s);
+void rescale_system(int64_t N, const int64_t *rowptr, const int32_t *col, double *vals, const double *sc,
+                    hipStream_t s);
+void scaling_from_diag(int64_t N, const double *vals, const int64_t *diag_pos, double *sc, hipStream_t s);
+void gather(int64_t n, const double *src, const int64_t *map, double *dst, hipStream_t s);
+void scale_vec(int64_t n, const double *x, const double *sc, double *y, int invert, hipStream_t s);
+
+// sparse and dense linear algebra
+template <typename TM, typename TX, typename TY>
+void spmv(int64_t nrows, const int64_t *rowptr, const int32_t *col, const TM *val, const TX *x, TY *y,
+          int64_t nnz, hipStream_t s);
+// y = b - A x
+template <typename T>
+void residual(int64_t n, const int64_t *rowptr, const int32_t *col, const T *val, const T *x, const T *b,
+              T *y, int64_t nnz, hipStream_t s);
+// Chebyshev step: x_out = x_in + d_new, d_new = c1 d + c2 (b - A x_in)  (first: x_in may be null => x_in = 0)
+template <typename T>
+void cheb_step(int64_t n, const int64_t *rowptr, const int32_t *col, const T *val, const T *x_in,
+               const T *b, T *d, T *x_out, double c1, double c2, int64_t nnz, hipStream_t s);
+// x += P xc
+template <typename T>
+void prolong_add(int64_t n, const int64_t *rowptr, const int32_t *col, const T *val, const T *xc, T *x,
+                 int64_t nnz, hipStream_t s);
+template <typename TA, typename TB>
+void convert(int64_t n, const TA *a, TB *b, hipStream_t s);
+void coarse_solve(int64_t n, const int32_t *comp, const int32_t *cloc, const int32_t *cmem, const int64_t *cstart,
+                  const int64_t *coff, const double *inv, const double *b, double *x, hipStream_t s);
+
+// Krylov helpers (deterministic two-stage reductions)
+void multi_dot(int64_t n, const double *V, int64_t ldv, int k, const double *w, double *out,
+               double *partial, int nblk, hipStream_t s);
+template <typename TZ>
+void multi_axpy(int64_t n, const TZ *Z, int64_t ldz, int k, const double *coef, double *x, hipStream_t s);
+void gs_update(int64_t n, const double *V, int64_t ldv, int k, const double *h, double *w,
+               double *partial, int nblk, hipStream_t s);   // w -= V h; partial norms
+void reduce_partials(int k, int nblk, const double *partial, double *out, hipStream_t s);
+void scale_by_inv_norm(int64_t n, const double *w, const double *nrm2, double *v, hipStream_t s);
+void add_scaled(int64_t n, double a, const double *x, double *y, hipStream_t s);   // y += a x
+void axpby(int64_t n, double a, const double *x, double b, double *y, hipStream_t s);
+void vmul(int64_t n, const double *a, const double *b, double *y, hipStream_t s);  // y = a .* b
+void sub(int64_t n, const double *a, const double *b, double *y, hipStream_t s);   // y = a - b
+int reduce_blocks(int64_t n);
+
+// adjoint
+void vjp_bulk(const RegionArgs &ra, const MeshArgs &ma, const PhysArgs &p, const int64_t *rowptr,
+              const double *u_prev, const double *u_n, const double *lam, double *u_prev_bar, hipStream_t s);
+void vjp_membrane(const GammaArgs &g, const MeshArgs &ma, const PhysArgs &p, int64_t Ni, int64_t Ne,
+                  const double *u_prev, const double *u_n, const double *lam, const double *theta,
+                  double *u_prev_bar, double *theta_bar_vertex, hipStream_t s);
+void reduce_theta(int64_t n_gamma, const int32_t *gcell, const double *per_vertex, int n_cells,
+                  double *theta_bar, hipStream_t s);
+
+}  // namespace launch
+}  // namespace knp

@@ -1,0 +1,397 @@
+// Sparse and dense linear-algebra kernels of the solver: CSR SpMV with fused
+// epilogues (residual, Chebyshev step, prolongation-add), the coarsest-level
+// dense solve, and the Krylov vector kernels with deterministic two-stage
+// reductions (classical Gram-Schmidt multi-dot and update, norms, axpys).
+//
+// SpMV maps a group of G lanes (G = 4..32, chosen from the mean row length) to
+// one CSR row: the group streams the row's column indices and values with
+// consecutive addresses and reduces its partial sums with cross-lane shuffles
+// inside the 64-wide wavefront.  All work is HBM-bound; nothing here is a dense
+// contraction, so no matrix-core instructions are involved.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "knp_internal.h"
+
+namespace knp {
+namespace launch {
+
+namespace {
+
+constexpr int TPB = 256;
+
+template <typename T>
+struct Acc {
+    using type = double;
+};
+template <>
+struct Acc<float> {
+    using type = float;   // FP32 levels accumulate in FP32
+};
+
+template <int G, typename A>
+__device__ inline A group_sum(A v) {
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, G);
+    return v;
+}
+
+template <typename T>
+__device__ inline T ldg_stream(const T *p) {
+    return __builtin_nontemporal_load(p);
+}
+
+template <int G, typename TM, typename TX, typename A>
+__device__ inline A row_dot(int64_t row, int lane, const int64_t *__restrict__ rowptr,
+                            const int32_t *__restrict__ col, const TM *__restrict__ val,
+                            const TX *__restrict__ x) {
+    const int64_t k0 = rowptr[row], k1 = rowptr[row + 1];
+    A s = A(0);
+    for (int64_t k = k0 + lane; k < k1; k += G) s += A(ldg_stream(val + k)) * A(x[ldg_stream(col + k)]);
+    return group_sum<G>(s);
+}
+
+template <int G, typename TM, typename TX, typename TY>
+__global__ void __launch_bounds__(TPB) k_spmv(int64_t nrows, const int64_t *__restrict__ rowptr,
+                                              const int32_t *__restrict__ col, const TM *__restrict__ val,
+                                              const TX *__restrict__ x, TY *__restrict__ y) {
+    using A = typename Acc<TM>::type;
+    const int64_t row = (int64_t(blockIdx.x) * TPB + threadIdx.x) / G;
+    const int lane = threadIdx.x % G;
+    if (row >= nrows) return;
+    const A s = row_dot<G, TM, TX, A>(row, lane, rowptr, col, val, x);
+    if (lane == 0) y[row] = TY(s);
+}
+
+template <int G, typename T>
+__global__ void __launch_bounds__(TPB) k_residual(int64_t nrows, const int64_t *__restrict__ rowptr,
+                                                  const int32_t *__restrict__ col, const T *__restrict__ val,
+                                                  const T *__restrict__ x, const T *__restrict__ b,
+                                                  T *__restrict__ y) {
+    using A = typename Acc<T>::type;
+    const int64_t row = (int64_t(blockIdx.x) * TPB + threadIdx.x) / G;
+    const int lane = threadIdx.x % G;
+    if (row >= nrows) return;
+    const A s = row_dot<G, T, T, A>(row, lane, rowptr, col, val, x);
+    if (lane == 0) y[row] = T(A(b[row]) - s);
+}
+
+// d <- c1 d + c2 (b - A x_in);  x_out <- x_in + d.   x_in == nullptr means x_in = 0.
+template <int G, typename T>
+__global__ void __launch_bounds__(TPB) k_cheb(int64_t nrows, const int64_t *__restrict__ rowptr,
+                                              const int32_t *__restrict__ col, const T *__restrict__ val,
+                                              const T *__restrict__ xin, const T *__restrict__ b,
+                                              T *__restrict__ d, T *__restrict__ xout, double c1, double c2) {
+    using A = typename Acc<T>::type;
+    const int64_t row = (int64_t(blockIdx.x) * TPB + threadIdx.x) / G;
+    const int lane = threadIdx.x % G;
+    if (row >= nrows) return;
+    A ax = A(0);
+    if (xin) ax = row_dot<G, T, T, A>(row, lane, rowptr, col, val, xin);
+    if (lane == 0) {
+        const A r = A(b[row]) - ax;
+        const A dn = (c1 == 0.0 ? A(0) : A(c1) * A(d[row])) + A(c2) * r;
+        d[row] = T(dn);
+        xout[row] = T((xin ? A(xin[row]) : A(0)) + dn);
+    }
+}
+
+template <int G, typename T>
+__global__ void __launch_bounds__(TPB) k_prolong_add(int64_t nrows, const int64_t *__restrict__ rowptr,
+                                                     const int32_t *__restrict__ col, const T *__restrict__ val,
+                                                     const T *__restrict__ xc, T *__restrict__ x) {
+    using A = typename Acc<T>::type;
+    const int64_t row = (int64_t(blockIdx.x) * TPB + threadIdx.x) / G;
+    const int lane = threadIdx.x % G;
+    if (row >= nrows) return;
+    const A s = row_dot<G, T, T, A>(row, lane, rowptr, col, val, xc);
+    if (lane == 0) x[row] = T(A(x[row]) + s);
+}
+
+template <typename TA, typename TB>
+__global__ void k_convert(int64_t n, const TA *__restrict__ a, TB *__restrict__ b) {
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+        b[i] = TB(a[i]);
+}
+
+// coarsest level: x = A_c^{-1} b with one dense inverse per connected component
+__global__ void __launch_bounds__(TPB) k_coarse(int64_t n, const int32_t *__restrict__ comp,
+                                                const int32_t *__restrict__ cloc, const int32_t *__restrict__ cmem,
+                                                const int64_t *__restrict__ cstart, const int64_t *__restrict__ coff,
+                                                const double *__restrict__ inv, const double *__restrict__ b,
+                                                double *__restrict__ x) {
+    const int64_t row = (int64_t(blockIdx.x) * TPB + threadIdx.x) / 64;
+    const int lane = threadIdx.x % 64;
+    if (row >= n) return;
+    const int32_t c = comp[row];
+    const int64_t s0 = cstart[c];
+    const int64_t nb = cstart[c + 1] - s0;
+    const double *ir = inv + coff[c] + int64_t(cloc[row]) * nb;
+    double s = 0.0;
+    for (int64_t p = lane; p < nb; p += 64) s += ir[p] * b[cmem[s0 + p]];
+    s = group_sum<64>(s);
+    if (lane == 0) x[row] = s;
+}
+
+// ---------------------------------------------------------------- reductions
+constexpr int KMAX = 16;
+
+__device__ inline double wave_sum(double v) { return group_sum<64>(v); }
+
+template <int K>
+__device__ inline void block_store_sums(double (&acc)[K], int k, double *__restrict__ out) {
+    __shared__ double sh[TPB / 64][K];
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        if (q < k) {
+            const double v = wave_sum(acc[q]);
+            if (lane == 0) sh[wave][q] = v;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < k) {
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < TPB / 64; ++w) s += sh[w][threadIdx.x];
+        out[threadIdx.x] = s;
+    }
+}
+
+__global__ void __launch_bounds__(TPB) k_multi_dot(int64_t n, const double *__restrict__ V, int64_t ldv, int k,
+                                                   const double *__restrict__ w, double *__restrict__ partial) {
+    double acc[KMAX];
+#pragma unroll
+    for (int q = 0; q < KMAX; ++q) acc[q] = 0.0;
+    for (int64_t i = int64_t(blockIdx.x) * TPB + threadIdx.x; i < n; i += int64_t(gridDim.x) * TPB) {
+        const double wi = w[i];
+#pragma unroll
+        for (int q = 0; q < KMAX; ++q)
+            if (q < k) acc[q] += V[q * ldv + i] * wi;
+    }
+    block_store_sums<KMAX>(acc, k, partial + int64_t(blockIdx.x) * KMAX);
+}
+
+__global__ void __launch_bounds__(TPB) k_gs_update(int64_t n, const double *__restrict__ V, int64_t ldv, int k,
+                                                   const double *__restrict__ h, double *__restrict__ w,
+                                                   double *__restrict__ partial) {
+    extern __shared__ double sh_h[];
+    for (int q = threadIdx.x; q < k; q += TPB) sh_h[q] = h[q];
+    __syncthreads();
+    double acc[1] = {0.0};
+    for (int64_t i = int64_t(blockIdx.x) * TPB + threadIdx.x; i < n; i += int64_t(gridDim.x) * TPB) {
+        double v = w[i];
+        for (int q = 0; q < k; ++q) v -= sh_h[q] * V[q * ldv + i];
+        w[i] = v;
+        acc[0] += v * v;
+    }
+    block_store_sums<1>(acc, 1, partial + int64_t(blockIdx.x) * KMAX);
+}
+
+__global__ void __launch_bounds__(TPB) k_reduce_partials(int nblk, const double *__restrict__ partial,
+                                                         double *__restrict__ out) {
+    const int q = blockIdx.x;
+    double acc[1] = {0.0};
+    for (int b = threadIdx.x; b < nblk; b += TPB) acc[0] += partial[int64_t(b) * KMAX + q];
+    block_store_sums<1>(acc, 1, out + q);
+}
+
+// w and v may alias (in-place normalisation)
+__global__ void k_scale_inv_norm(int64_t n, const double *w, const double *__restrict__ nrm2, double *v) {
+    const double s = 1.0 / sqrt(nrm2[0]);
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+        v[i] = w[i] * s;
+}
+
+template <typename TZ>
+__global__ void k_multi_axpy(int64_t n, const TZ *__restrict__ Z, int64_t ldz, int k, const double *__restrict__ c,
+                             double *__restrict__ x) {
+    extern __shared__ double sh_c[];
+    for (int q = threadIdx.x; q < k; q += blockDim.x) sh_c[q] = c[q];
+    __syncthreads();
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
+        double s = x[i];
+        for (int q = 0; q < k; ++q) s += sh_c[q] * double(Z[q * ldz + i]);
+        x[i] = s;
+    }
+}
+
+__global__ void k_axpby(int64_t n, double a, const double *x, double b, double *y) {
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+        y[i] = a * x[i] + (b == 0.0 ? 0.0 : b * y[i]);
+}
+
+__global__ void k_vmul(int64_t n, const double *a, const double *b, double *y) {
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+        y[i] = a[i] * b[i];
+}
+
+// operands may alias the output (element-wise)
+__global__ void k_sub(int64_t n, const double *a, const double *b, double *y) {
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+        y[i] = a[i] - b[i];
+}
+
+inline unsigned grid_for(int64_t n, int per_block) {
+    int64_t g = (n + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    return unsigned(g);
+}
+
+inline unsigned stream_grid(int64_t n) {
+    int64_t g = (n + TPB - 1) / TPB;
+    if (g > 4096) g = 4096;
+    if (g < 1) g = 1;
+    return unsigned(g);
+}
+
+// group width from the mean row length
+inline int pick_group(int64_t nrows, int64_t nnz) {
+    const double avg = nrows ? double(nnz) / double(nrows) : 0.0;
+    if (avg <= 6.0) return 4;
+    if (avg <= 20.0) return 8;
+    if (avg <= 48.0) return 16;
+    return 32;
+}
+
+#define KNP_DISPATCH_G(G_, ...)                              \
+    switch (G_) {                                            \
+        case 4: { constexpr int G = 4; __VA_ARGS__; } break;   \
+        case 8: { constexpr int G = 8; __VA_ARGS__; } break;   \
+        case 16: { constexpr int G = 16; __VA_ARGS__; } break; \
+        default: { constexpr int G = 32; __VA_ARGS__; } break; \
+    }
+
+}  // namespace
+
+int reduce_blocks(int64_t n) {
+    int64_t b = (n + TPB * 8 - 1) / (TPB * 8);
+    if (b > 1024) b = 1024;
+    if (b < 1) b = 1;
+    return int(b);
+}
+
+template <typename TM, typename TX, typename TY>
+void spmv(int64_t nrows, const int64_t *rowptr, const int32_t *col, const TM *val, const TX *x, TY *y,
+          int64_t nnz, hipStream_t s) {
+    if (nrows == 0) return;
+    const int g = pick_group(nrows, nnz);
+    KNP_DISPATCH_G(g, hipLaunchKernelGGL((k_spmv<G, TM, TX, TY>), dim3(grid_for(nrows * G, TPB)), dim3(TPB), 0, s,
+                                         nrows, rowptr, col, val, x, y));
+}
+
+template <typename T>
+void residual(int64_t n, const int64_t *rowptr, const int32_t *col, const T *val, const T *x, const T *b, T *y,
+              int64_t nnz, hipStream_t s) {
+    if (n == 0) return;
+    const int g = pick_group(n, nnz);
+    KNP_DISPATCH_G(g, hipLaunchKernelGGL((k_residual<G, T>), dim3(grid_for(n * G, TPB)), dim3(TPB), 0, s, n, rowptr,
+                                         col, val, x, b, y));
+}
+
+template <typename T>
+void cheb_step(int64_t n, const int64_t *rowptr, const int32_t *col, const T *val, const T *x_in, const T *b, T *d,
+               T *x_out, double c1, double c2, int64_t nnz, hipStream_t s) {
+    if (n == 0) return;
+    const int g = pick_group(n, nnz);
+    KNP_DISPATCH_G(g, hipLaunchKernelGGL((k_cheb<G, T>), dim3(grid_for(n * G, TPB)), dim3(TPB), 0, s, n, rowptr,
+                                         col, val, x_in, b, d, x_out, c1, c2));
+}
+
+template <typename T>
+void prolong_add(int64_t n, const int64_t *rowptr, const int32_t *col, const T *val, const T *xc, T *x, int64_t nnz,
+                 hipStream_t s) {
+    if (n == 0) return;
+    const int g = pick_group(n, nnz);
+    KNP_DISPATCH_G(g, hipLaunchKernelGGL((k_prolong_add<G, T>), dim3(grid_for(n * G, TPB)), dim3(TPB), 0, s, n,
+                                         rowptr, col, val, xc, x));
+}
+
+template <typename TA, typename TB>
+void convert(int64_t n, const TA *a, TB *b, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL((k_convert<TA, TB>), dim3(stream_grid(n)), dim3(TPB), 0, s, n, a, b);
+}
+
+void coarse_solve(int64_t n, const int32_t *comp, const int32_t *cloc, const int32_t *cmem, const int64_t *cstart,
+                  const int64_t *coff, const double *inv, const double *b, double *x, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_coarse, dim3(grid_for(n * 64, TPB)), dim3(TPB), 0, s, n, comp, cloc, cmem, cstart, coff, inv,
+                       b, x);
+}
+
+void multi_dot(int64_t n, const double *V, int64_t ldv, int k, const double *w, double *out, double *partial,
+               int nblk, hipStream_t s) {
+    for (int q0 = 0; q0 < k; q0 += KMAX) {
+        const int kk = std::min(KMAX, k - q0);
+        hipLaunchKernelGGL(k_multi_dot, dim3(nblk), dim3(TPB), 0, s, n, V + q0 * ldv, ldv, kk, w, partial);
+        hipLaunchKernelGGL(k_reduce_partials, dim3(kk), dim3(TPB), 0, s, nblk, partial, out + q0);
+    }
+}
+
+void gs_update(int64_t n, const double *V, int64_t ldv, int k, const double *h, double *w, double *partial, int nblk,
+               hipStream_t s) {
+    hipLaunchKernelGGL(k_gs_update, dim3(nblk), dim3(TPB), size_t(k > 0 ? k : 1) * sizeof(double), s, n, V, ldv, k, h,
+                       w, partial);
+}
+
+void reduce_partials(int k, int nblk, const double *partial, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce_partials, dim3(k), dim3(TPB), 0, s, nblk, partial, out);
+}
+
+void scale_by_inv_norm(int64_t n, const double *w, const double *nrm2, double *v, hipStream_t s) {
+    hipLaunchKernelGGL(k_scale_inv_norm, dim3(stream_grid(n)), dim3(TPB), 0, s, n, w, nrm2, v);
+}
+
+template <typename TZ>
+void multi_axpy(int64_t n, const TZ *Z, int64_t ldz, int k, const double *coef, double *x, hipStream_t s) {
+    if (k == 0) return;
+    hipLaunchKernelGGL((k_multi_axpy<TZ>), dim3(stream_grid(n)), dim3(TPB), size_t(k) * sizeof(double), s, n, Z, ldz,
+                       k, coef, x);
+}
+
+void add_scaled(int64_t n, double a, const double *x, double *y, hipStream_t s) {
+    // y += a x
+    hipLaunchKernelGGL(k_axpby, dim3(stream_grid(n)), dim3(TPB), 0, s, n, a, x, 1.0, y);
+}
+
+void axpby(int64_t n, double a, const double *x, double b, double *y, hipStream_t s) {
+    hipLaunchKernelGGL(k_axpby, dim3(stream_grid(n)), dim3(TPB), 0, s, n, a, x, b, y);
+}
+
+void vmul(int64_t n, const double *a, const double *b, double *y, hipStream_t s) {
+    hipLaunchKernelGGL(k_vmul, dim3(stream_grid(n)), dim3(TPB), 0, s, n, a, b, y);
+}
+
+void sub(int64_t n, const double *a, const double *b, double *y, hipStream_t s) {
+    hipLaunchKernelGGL(k_sub, dim3(stream_grid(n)), dim3(TPB), 0, s, n, a, b, y);
+}
+
+// explicit instantiations
+template void spmv<double, double, double>(int64_t, const int64_t *, const int32_t *, const double *,
+                                           const double *, double *, int64_t, hipStream_t);
+template void spmv<double, float, double>(int64_t, const int64_t *, const int32_t *, const double *, const float *,
+                                          double *, int64_t, hipStream_t);
+template void spmv<float, float, float>(int64_t, const int64_t *, const int32_t *, const float *, const float *,
+                                        float *, int64_t, hipStream_t);
+template void residual<double>(int64_t, const int64_t *, const int32_t *, const double *, const double *,
+                               const double *, double *, int64_t, hipStream_t);
+template void residual<float>(int64_t, const int64_t *, const int32_t *, const float *, const float *, const float *,
+                              float *, int64_t, hipStream_t);
+template void cheb_step<double>(int64_t, const int64_t *, const int32_t *, const double *, const double *,
+                                const double *, double *, double *, double, double, int64_t, hipStream_t);
+template void cheb_step<float>(int64_t, const int64_t *, const int32_t *, const float *, const float *, const float *,
+                               float *, float *, double, double, int64_t, hipStream_t);
+template void prolong_add<double>(int64_t, const int64_t *, const int32_t *, const double *, const double *, double *,
+                                  int64_t, hipStream_t);
+template void prolong_add<float>(int64_t, const int64_t *, const int32_t *, const float *, const float *, float *,
+                                 int64_t, hipStream_t);
+template void convert<double, float>(int64_t, const double *, float *, hipStream_t);
+template void convert<float, double>(int64_t, const float *, double *, hipStream_t);
+template void convert<double, double>(int64_t, const double *, double *, hipStream_t);
+template void multi_axpy<double>(int64_t, const double *, int64_t, int, const double *, double *, hipStream_t);
+template void multi_axpy<float>(int64_t, const float *, int64_t, int, const double *, double *, hipStream_t);
+
+}  // namespace launch
+}  // namespace knp

@@ -1,0 +1,227 @@
+// Flexible GMRES(m) with classical Gram-Schmidt for A_{n-1} u_n = f_n and for
+// the adjoint system, preconditioned on the right by one AMG V-cycle on P_0
+// (Sec. "Solution and preconditioning strategy"; restart 30 and the previous
+// step as initial guess, Sec. "Solver configurations").
+//
+// The iteration runs on the symmetrically scaled system (S A S) y = S b,
+// x = S y, S = diag(P_0)^{-1/2}; its stopping test is ||S(b - A x)|| <= rtol ||S b||.
+// Right preconditioning keeps the true residual available and lets the
+// preconditioner vary between iterations, so the same recurrence serves the
+// FP64 and the FP32 V-cycle.  Arnoldi, the Hessenberg least-squares problem,
+// the solution update and the true-residual recomputation are FP64.
+// One device-to-host copy of the new Hessenberg column per iteration.
+#include <cmath>
+#include <cstring>
+
+#include "ctx.h"
+
+namespace knp {
+
+namespace {
+
+double dev_dot(knp_ctx *c, const double *a, const double *b, int64_t n) {
+    // <a, b> via the multi-dot kernel with one vector (deterministic)
+    launch::multi_dot(n, a, n, 1, b, c->dscal.p, c->partial.p, c->nblk, c->stream);
+    double h = 0.0;
+    hip_check(hipMemcpyAsync(&h, c->dscal.p, sizeof(double), hipMemcpyDeviceToHost, c->stream), "dot copy");
+    hip_check(hipStreamSynchronize(c->stream), "dot sync");
+    return h;
+}
+
+void ensure_workspace(knp_ctx *c, int m, bool z32) {
+    const int64_t N = c->hm.N;
+    if (c->m_alloc >= m && c->z32 == z32) return;
+    c->V.release();
+    c->Z64.release();
+    c->Z32.release();
+    c->V.alloc(size_t(m + 1) * N);
+    if (z32)
+        c->Z32.alloc(size_t(m) * N);
+    else
+        c->Z64.alloc(size_t(m) * N);
+    c->dscal.release();
+    c->dscal.alloc(size_t(m) + 64);
+    c->m_alloc = m;
+    c->z32 = z32;
+}
+
+}  // namespace
+
+void apply_operator(knp_ctx *c, bool transpose, const double *x, double *y) {
+    const int64_t N = c->hm.N;
+    hipEvent_t t0 = c->tm.begin(KNP_TIMER_SPMV_A, c->stream);
+    if (transpose)
+        launch::spmv<double, double, double>(N, c->d_rowptrT.p, c->d_colT.p, c->d_valsT.p, x, y, c->hm.nnz, c->stream);
+    else
+        launch::spmv<double, double, double>(N, c->d_rowptr.p, c->d_colidx.p, c->d_vals.p, x, y, c->hm.nnz, c->stream);
+    c->tm.end(KNP_TIMER_SPMV_A, t0, 12.0 * double(c->hm.nnz) + 32.0 * double(N) + 8.0, c->stream);
+}
+
+knp_status krylov_solve(knp_ctx *c, bool transpose, const double *b, double *x, const knp_solve_opts &o,
+                        knp_solve_info *info) {
+    const int64_t N = c->hm.N;
+    hipStream_t s = c->stream;
+    const bool use_amg = o.precond == 1;
+    if (use_amg && !c->amg.ready) throw Error{KNP_E_STATE, "knp_amg_setup has not been called"};
+    const int m = o.restart;
+    const bool z32 = use_amg && c->amg.fp32;
+    ensure_workspace(c, m, z32);
+    if (transpose) ensure_transpose(c);
+    double *bh = c->bh.p, *yh = c->yh.p, *w = c->w.p;
+    launch::vmul(N, b, c->d_sc.p, bh, s);
+    launch::scale_vec(N, x, c->d_sc.p, yh, 1, s);
+    const double bnorm = std::sqrt(dev_dot(c, bh, bh, N));
+    knp_solve_info inf{};
+    if (!std::isfinite(bnorm)) throw Error{KNP_E_NUMERIC, "NaN or Inf in the right-hand side"};
+    if (bnorm == 0.0) {
+        hip_check(hipMemsetAsync(x, 0, size_t(N) * sizeof(double), s), "zero x");
+        hip_check(hipStreamSynchronize(s), "sync");
+        if (info) *info = inf;
+        return KNP_OK;
+    }
+    std::vector<double> H(size_t(m + 1) * m), cs(m), sn(m), g(m + 1), hcol(m + 2), hcol2(m + 2), y(m);
+    auto Hc = [&](int i, int j) -> double & { return H[size_t(j) * (m + 1) + i]; };
+    int its = 0, restarts = 0;
+    double est = 1.0;
+    bool converged = false;
+    while (true) {
+        apply_operator(c, transpose, yh, w);
+        launch::sub(N, bh, w, w, s);
+        const double beta = std::sqrt(dev_dot(c, w, w, N));
+        if (!std::isfinite(beta)) throw Error{KNP_E_NUMERIC, "NaN or Inf in the residual"};
+        est = beta / bnorm;
+        if (est <= o.rtol) {
+            converged = true;
+            break;
+        }
+        if (its >= o.max_it) break;
+        ++restarts;
+        double *V = c->V.p;
+        launch::axpby(N, 1.0 / beta, w, 0.0, V, s);
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        int jend = 0;
+        for (int j = 0; j < m; ++j) {
+            const double *vj = V + size_t(j) * N;
+            double *wj = V + size_t(j + 1) * N;
+            if (use_amg) {
+                if (z32) {
+                    float *zj = c->Z32.p + size_t(j) * N;
+                    amg_vcycle(c->amg, vj, zj, s, &c->tm);
+                    hipEvent_t t0 = c->tm.begin(KNP_TIMER_SPMV_A, s);
+                    launch::spmv<double, float, double>(N, transpose ? c->d_rowptrT.p : c->d_rowptr.p,
+                                                        transpose ? c->d_colT.p : c->d_colidx.p,
+                                                        transpose ? c->d_valsT.p : c->d_vals.p, zj, wj, c->hm.nnz,
+                                                        s);
+                    c->tm.end(KNP_TIMER_SPMV_A, t0, 12.0 * double(c->hm.nnz) + 28.0 * double(N) + 8.0, s);
+                } else {
+                    double *zj = c->Z64.p + size_t(j) * N;
+                    amg_vcycle(c->amg, vj, zj, s, &c->tm);
+                    apply_operator(c, transpose, zj, wj);
+                }
+            } else {
+                apply_operator(c, transpose, vj, wj);
+            }
+            // classical Gram-Schmidt (optionally twice)
+            double *dh = c->dscal.p;
+            launch::multi_dot(N, V, N, j + 1, wj, dh, c->partial.p, c->nblk, s);
+            launch::gs_update(N, V, N, j + 1, dh, wj, c->partial.p, c->nblk, s);
+            if (o.reorth) {
+                hip_check(hipMemcpyAsync(hcol.data(), dh, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, s), "h");
+                launch::multi_dot(N, V, N, j + 1, wj, dh, c->partial.p, c->nblk, s);
+                launch::gs_update(N, V, N, j + 1, dh, wj, c->partial.p, c->nblk, s);
+                hip_check(hipMemcpyAsync(hcol2.data(), dh, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, s), "h2");
+            }
+            launch::reduce_partials(1, c->nblk, c->partial.p, dh + m + 1, s);
+            if (!o.reorth)
+                hip_check(hipMemcpyAsync(hcol.data(), dh, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, s), "h");
+            double nrm2 = 0.0;
+            hip_check(hipMemcpyAsync(&nrm2, dh + m + 1, sizeof(double), hipMemcpyDeviceToHost, s), "nrm");
+            hip_check(hipStreamSynchronize(s), "gs sync");
+            const double hn = std::sqrt(nrm2);
+            if (!std::isfinite(hn)) throw Error{KNP_E_NUMERIC, "NaN or Inf in the Arnoldi process"};
+            for (int i = 0; i <= j; ++i) Hc(i, j) = hcol[i] + (o.reorth ? hcol2[i] : 0.0);
+            Hc(j + 1, j) = hn;
+            if (hn > 0.0) launch::scale_by_inv_norm(N, wj, dh + m + 1, wj, s);
+            // Givens rotations
+            for (int i = 0; i < j; ++i) {
+                const double t = cs[i] * Hc(i, j) + sn[i] * Hc(i + 1, j);
+                Hc(i + 1, j) = -sn[i] * Hc(i, j) + cs[i] * Hc(i + 1, j);
+                Hc(i, j) = t;
+            }
+            const double den = std::hypot(Hc(j, j), Hc(j + 1, j));
+            cs[j] = den > 0.0 ? Hc(j, j) / den : 1.0;
+            sn[j] = den > 0.0 ? Hc(j + 1, j) / den : 0.0;
+            Hc(j, j) = den;
+            Hc(j + 1, j) = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            ++its;
+            jend = j + 1;
+            est = std::fabs(g[j + 1]) / bnorm;
+            if (est <= o.rtol || its >= o.max_it || hn == 0.0) break;
+        }
+        // y = H^{-1} g (upper triangular), x += Z y
+        for (int i = jend - 1; i >= 0; --i) {
+            double t = g[i];
+            for (int k = i + 1; k < jend; ++k) t -= Hc(i, k) * y[k];
+            y[i] = Hc(i, i) != 0.0 ? t / Hc(i, i) : 0.0;
+        }
+        hip_check(hipMemcpyAsync(c->dscal.p, y.data(), sizeof(double) * jend, hipMemcpyHostToDevice, s), "y");
+        if (!use_amg)
+            launch::multi_axpy<double>(N, c->V.p, N, jend, c->dscal.p, yh, s);
+        else if (z32)
+            launch::multi_axpy<float>(N, c->Z32.p, N, jend, c->dscal.p, yh, s);
+        else
+            launch::multi_axpy<double>(N, c->Z64.p, N, jend, c->dscal.p, yh, s);
+        hip_check(hipStreamSynchronize(s), "update sync");
+        inf.rel_res_est = est;
+    }
+    // true residual of the final iterate
+    apply_operator(c, transpose, yh, w);
+    launch::sub(N, bh, w, w, s);
+    inf.rel_res = std::sqrt(dev_dot(c, w, w, N)) / bnorm;
+    if (converged) inf.rel_res_est = est;
+    inf.its = its;
+    inf.restarts = restarts;
+    launch::vmul(N, yh, c->d_sc.p, x, s);
+    hip_check(hipStreamSynchronize(s), "solve sync");
+    c->tm.harvest();
+    if (info) *info = inf;
+    if (!converged && !(inf.rel_res <= o.rtol)) return KNP_E_NOCONV;
+    return KNP_OK;
+}
+
+void ensure_transpose(knp_ctx *c) {
+    const HostMesh &m = c->hm;
+    hipStream_t s = c->stream;
+    if (!c->have_T) {
+        std::vector<int64_t> rpT(m.N + 1, 0), perm(m.nnz);
+        std::vector<int32_t> colT(m.nnz);
+        for (int64_t k = 0; k < m.nnz; ++k) rpT[m.colidx[k] + 1]++;
+        for (int64_t i = 0; i < m.N; ++i) rpT[i + 1] += rpT[i];
+        std::vector<int64_t> fill(rpT.begin(), rpT.end() - 1);
+        for (int64_t i = 0; i < m.N; ++i)
+            for (int64_t k = m.rowptr[i]; k < m.rowptr[i + 1]; ++k) {
+                const int64_t p = fill[m.colidx[k]]++;
+                colT[p] = int32_t(i);
+                perm[p] = k;
+            }
+        c->d_rowptrT.alloc(m.N + 1);
+        c->d_rowptrT.upload(rpT, s);
+        c->d_colT.alloc(m.nnz);
+        c->d_colT.upload(colT, s);
+        c->d_permT.alloc(m.nnz);
+        c->d_permT.upload(perm, s);
+        c->d_valsT.alloc(m.nnz);
+        hip_check(hipStreamSynchronize(s), "transpose upload");
+        c->have_T = true;
+        c->T_current = false;
+    }
+    if (!c->T_current) {
+        launch::gather(m.nnz, c->d_vals.p, c->d_permT.p, c->d_valsT.p, s);
+        c->T_current = true;
+    }
+}
+
+}  // namespace knp

@@ -1,0 +1,75 @@
+"""Time loop on the device: for n = 1..N_t assemble A_{n-1}, f_n and solve with
+GMRES + AMG(P_0) (Sec. "Time discretization", Sec. "Solver configurations").
+P_0 and its hierarchy are built once, after the first assembly."""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from .knp import Context, amg_opts, solve_opts
+
+
+def initial_vector(case, dof_vertex, info):
+    """u_0 in the library's DOF layout from per-vertex initial data."""
+    u0 = np.empty(info.N)
+    Nr = (info.N_i, info.N_e)
+    off = (0, 4 * info.N_i)
+    for r in (0, 1):
+        for f in range(4):
+            sl = slice(off[r] + f * Nr[r], off[r] + (f + 1) * Nr[r])
+            u0[sl] = case.conc0[r, f, dof_vertex[sl]] if f < 3 else case.phi0[r]
+    return u0
+
+
+class KnpSolver:
+    """Holds one context and the state (u, gates) of a run on one GPU."""
+
+    def __init__(self, case, device=0, amg=None, solve=None, theta=None):
+        self.case = case
+        self.dev = torch.device("cuda", device)
+        self.ctx = Context(device)
+        self.info = self.ctx.mesh_upload(case.dim, case.xyz, case.elem, case.tag, case.pin_vertex)
+        self.ctx.set_params(case.params, case.cell_model, case.cell_stim)
+        self.rowptr, self.colidx, self.dof_vertex = self.ctx.get_layout()
+        self.gamma = self.ctx.get_gamma()
+        u0 = initial_vector(case, self.dof_vertex, self.info)
+        self.u = torch.tensor(u0, dtype=torch.float64, device=self.dev)
+        g0 = np.tile(np.asarray(case.params["gates0"], dtype=np.float64), (self.info.n_gamma, 1))
+        self.gates = torch.tensor(g0, dtype=torch.float64, device=self.dev).contiguous()
+        th = case.theta if theta is None else theta
+        self.theta = torch.as_tensor(np.asarray(th, dtype=np.float64), device=self.dev).contiguous()
+        self.f = torch.empty(self.info.N, dtype=torch.float64, device=self.dev)
+        self.amg_opts = amg if amg is not None else amg_opts()
+        self.solve_opts = solve if solve is not None else solve_opts()
+        self.amg_ready = False
+        self.n = 0
+        self.history = []
+
+    def assemble(self, n=None):
+        n = self.n + 1 if n is None else n
+        self.ctx.assemble_step(n * self.case.dt, self.case.dt, self.u, self.gates, self.theta, self.f)
+        if not self.amg_ready:
+            self.ctx.amg_setup(self.amg_opts)
+            self.amg_ready = True
+
+    def solve(self, allow_noconv=False, opts=None):
+        x = self.u.clone()
+        info, ok = self.ctx.gmres_solve(self.f, x, opts if opts is not None else self.solve_opts,
+                                        allow_noconv=allow_noconv)
+        return x, info, ok
+
+    def step(self, allow_noconv=False, opts=None):
+        self.assemble()
+        x, info, ok = self.solve(allow_noconv, opts)
+        self.u = x
+        self.n += 1
+        self.history.append({"n": self.n, "its": info.its, "rel_res": info.rel_res, "converged": ok})
+        return info
+
+    def run(self, n_steps=None):
+        n_steps = self.case.n_steps if n_steps is None else n_steps
+        out = [self.u.clone()]
+        for _ in range(n_steps):
+            self.step()
+            out.append(self.u.clone())
+        return out
