@@ -37,13 +37,13 @@ def block_errors(info, u, ref):
     return out
 
 
-def run_precision(solver, u0, g0, precision, warmup, steps, log, first_restart):
+def run_precision(solver, u0, g0, precision, warmup, steps, log, first_restart, amg_kw):
     import torch
     from paper_2403_04491_amd import amg_opts, solve_opts
     solver.u = u0.clone()
     solver.gates = g0.clone()
     solver.n = 0
-    solver.amg_opts = amg_opts(precision=precision)
+    solver.amg_opts = amg_opts(precision=precision, **amg_kw)
     solver.amg_ready = False
     t_setup = time.perf_counter()
     its_w = []
@@ -134,6 +134,11 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--first-restart", type=int, default=200,
                     help="FGMRES restart of the untimed first step (later steps: 30)")
+    ap.add_argument("--restart", type=int, default=30)
+    ap.add_argument("--cheb-degree", type=int, default=2)
+    ap.add_argument("--cheb-ratio", type=float, default=10.0)
+    ap.add_argument("--strength", type=float, default=0.25)
+    ap.add_argument("--coarse-max", type=int, default=2000)
     ap.add_argument("--quiet", action="store_true")
     args = ap.parse_args()
 
@@ -156,7 +161,9 @@ def main():
     t_gen = time.perf_counter() - t0
     log(f"case {case.name}: {case.n_vert} vertices, {case.n_elem} tets, generated in {t_gen:.1f} s")
     t0 = time.perf_counter()
-    solver = KnpSolver(case, solve=solve_opts(rtol=1e-6, restart=30, max_it=2000))
+    amg_kw = dict(cheb_degree=args.cheb_degree, cheb_ratio=args.cheb_ratio, strength=args.strength,
+                  coarse_max=args.coarse_max)
+    solver = KnpSolver(case, solve=solve_opts(rtol=1e-6, restart=args.restart, max_it=2000))
     torch.cuda.synchronize()
     t_upload = time.perf_counter() - t0
     info = solver.info
@@ -168,7 +175,8 @@ def main():
     for prec in order:
         name = "fp64" if prec == 0 else "fp32_amg"
         log(f"[{name}]")
-        runs[name] = run_precision(solver, u0, g0, prec, args.warmup, args.steps, log, args.first_restart)
+        runs[name] = run_precision(solver, u0, g0, prec, args.warmup, args.steps, log, args.first_restart,
+                                   amg_kw)
     head = runs.get("fp32_amg") or runs["fp64"]
     kernel, roof = roofline_of(head["timers"])
     extra = {}
@@ -192,8 +200,9 @@ def main():
         "dtype": "f64 (AMG levels f32)" if "fp32_amg" in runs else "f64",
         "data": "synthetic",
         "config": {"workload": f"4x4x4 lattice of jittered box cells, {case.shape[0]}^3 grid x 6 tets, "
-                               f"N={info.N} unknowns, 16 HH + 48 leak cells, dt=0.05 ms, FGMRES(30) rtol 1e-6",
-                   "N": info.N, "nnz_A": info.nnz_A, "nnz_P0": info.nnz_P0, "parallelism": "1 GPU"},
+                               f"N={info.N} unknowns, 16 HH + 48 leak cells, dt=0.05 ms, FGMRES({args.restart}) rtol 1e-6",
+                   "N": info.N, "nnz_A": info.nnz_A, "nnz_P0": info.nnz_P0, "parallelism": "1 GPU",
+                   "amg": amg_kw},
         "its_per_step": {k: float(sum(r["its"]) / len(r["its"])) for k, r in runs.items()},
         "steps_per_s": {k: round(r["steps_per_s"], 3) for k, r in runs.items()},
         "ms_per_step_by_precision": {k: round(r["ms_per_step"], 2) for k, r in runs.items()},

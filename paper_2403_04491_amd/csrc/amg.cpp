@@ -255,12 +255,33 @@ void invert_dense(int n, std::vector<double> &a) {   // Gauss-Jordan, partial pi
 
 }  // namespace
 
+std::vector<int32_t> row_blocks(const int64_t *rowptr, int64_t nrows) {
+    std::vector<int32_t> b;
+    b.push_back(0);
+    int64_t r = 0;
+    while (r < nrows) {
+        const int64_t k0 = rowptr[r];
+        int64_t e = r;
+        while (e < nrows && rowptr[e + 1] - k0 <= STREAM_CAP && e - r < STREAM_CAP) ++e;
+        if (e == r) throw Error{KNP_E_ARG, "a matrix row is longer than the streaming block capacity"};
+        b.push_back(int32_t(e));
+        r = e;
+    }
+    return b;
+}
+
 void DevCsr::upload(const Csr &h, bool fp32, hipStream_t s) {
     nrows = h.nrows;
     ncols = h.ncols;
     nnz = h.nnz();
     rowptr.alloc(h.rowptr.size());
     rowptr.upload(h.rowptr, s);
+    {
+        std::vector<int32_t> b = row_blocks(h.rowptr.data(), h.nrows);
+        nblk = int64_t(b.size()) - 1;
+        blk.alloc(b.size());
+        blk.upload(b, s);
+    }
     col.alloc(std::max<size_t>(1, h.col.size()));
     if (!h.col.empty()) col.upload(h.col, s);
     if (fp32) {
@@ -605,8 +626,6 @@ T *vcycle_level(Amg &amg, size_t l, const T *b, hipStream_t s, Timers *tm) {
     std::vector<std::pair<double, double>> cc;
     cheb_coeffs(L->lmax, amg.ratio, amg.degree, cc);
     const int64_t n = L->n, nnz = L->A.nnz;
-    const int64_t *rp = L->A.rowptr.p;
-    const int32_t *ci = L->A.col.p;
     const T *av = LV<T>::A(L);
     T *x = LV<T>::x(L), *x2 = LV<T>::x2(L), *d = LV<T>::d(L), *t = LV<T>::t(L);
     // algorithmic bytes: values + column indices once, row pointers, each vector once
@@ -615,7 +634,7 @@ T *vcycle_level(Amg &amg, size_t l, const T *b, hipStream_t s, Timers *tm) {
     Timers *t0 = (l == 0) ? tm : nullptr;
     auto cheb = [&](const T *xin, T *xout, double c1, double c2) {
         hipEvent_t e = t0 ? t0->begin(KNP_TIMER_CHEB_L0, s) : nullptr;
-        launch::cheb_step<T>(n, rp, ci, av, xin, b, d, xout, c1, c2, nnz, s);
+        launch::cheb_step<T>(L->A.view(), av, xin, b, d, xout, c1, c2, s);
         if (t0) {
             const double bytes = xin ? mat + vb * double(n) * (c1 != 0.0 ? 5.0 : 4.0) : 3.0 * vb * double(n);
             t0->end(KNP_TIMER_CHEB_L0, e, bytes, s);
@@ -630,14 +649,14 @@ T *vcycle_level(Amg &amg, size_t l, const T *b, hipStream_t s, Timers *tm) {
     // residual and restriction
     {
         hipEvent_t e = t0 ? t0->begin(KNP_TIMER_RESID_L0, s) : nullptr;
-        launch::residual<T>(n, rp, ci, av, x, b, t, nnz, s);
+        launch::residual<T>(L->A.view(), av, x, b, t, s);
         if (t0) t0->end(KNP_TIMER_RESID_L0, e, mat + 3.0 * vb * double(n), s);
     }
     Level *Lc = amg.levels[l + 1];
     T *bc = LV<T>::b(Lc);
-    launch::spmv<T, T, T>(L->R.nrows, L->R.rowptr.p, L->R.col.p, LV<T>::R(L), t, bc, L->R.nnz, s);
+    launch::spmv<T, T, T>(L->R.view(), LV<T>::R(L), t, bc, s);
     T *xc = vcycle_level<T>(amg, l + 1, bc, s, tm);
-    launch::prolong_add<T>(n, L->P.rowptr.p, L->P.col.p, LV<T>::P(L), xc, x, L->P.nnz, s);
+    launch::prolong_add<T>(L->P.view(), LV<T>::P(L), xc, x, s);
     // post-smoothing
     for (size_t k = 0; k < cc.size(); ++k) {
         cheb(x, x2, cc[k].first, cc[k].second);

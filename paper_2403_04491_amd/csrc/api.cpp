@@ -310,6 +310,12 @@ knp_status knp_mesh_upload(knp_ctx *c, int dim, int64_t n_vert, const double *xy
             c->d_colidx.upload(h.colidx, s);
             c->d_diag.alloc(h.diag_pos.size());
             c->d_diag.upload(h.diag_pos, s);
+            {
+                std::vector<int32_t> b = row_blocks(h.rowptr.data(), h.N);
+                c->nblkA = int64_t(b.size()) - 1;
+                c->d_blkA.alloc(b.size());
+                c->d_blkA.upload(b, s);
+            }
             c->d_vals.alloc(h.nnz);
             c->d_sc.alloc(h.N);
             c->nblk = launch::reduce_blocks(h.N);

@@ -35,6 +35,8 @@ struct knp_ctx {
     knp::DArray<int64_t> d_rowptr, d_diag;
     knp::DArray<int32_t> d_colidx;
     knp::DArray<double> d_vals, d_sc;
+    knp::DArray<int32_t> d_blkA;
+    int64_t nblkA = 0;
     knp::DArray<int32_t> d_flag;
     double dt_static = -1.0;
     double dt_first = -1.0;
@@ -42,7 +44,8 @@ struct knp_ctx {
     // transposed system (adjoint)
     bool have_T = false, T_current = false;
     knp::DArray<int64_t> d_rowptrT, d_permT;
-    knp::DArray<int32_t> d_colT;
+    knp::DArray<int32_t> d_colT, d_blkT;
+    int64_t nblkT = 0;
     knp::DArray<double> d_valsT;
 
     // preconditioner
@@ -63,6 +66,26 @@ struct knp_ctx {
     knp::launch::MeshArgs mesh_args() const;
     knp::launch::GammaArgs gamma_args() const;
     knp::launch::PhysArgs phys(double t, double dt) const;
+    knp::CsrView viewA() const {
+        knp::CsrView v;
+        v.nrows = hm.N;
+        v.nnz = hm.nnz;
+        v.nblk = nblkA;
+        v.rowptr = d_rowptr.p;
+        v.col = d_colidx.p;
+        v.blk = d_blkA.p;
+        return v;
+    }
+    knp::CsrView viewT() const {
+        knp::CsrView v;
+        v.nrows = hm.N;
+        v.nnz = hm.nnz;
+        v.nblk = nblkT;
+        v.rowptr = d_rowptrT.p;
+        v.col = d_colT.p;
+        v.blk = d_blkT.p;
+        return v;
+    }
 };
 
 namespace knp {

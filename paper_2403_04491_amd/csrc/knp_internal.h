@@ -124,13 +124,39 @@ struct Csr {
     int64_t nnz() const { return rowptr.empty() ? 0 : rowptr.back(); }
 };
 
+// Device view of a CSR pattern for the block-streamed kernels: blk[b]..blk[b+1]
+// are the rows of block b, whose entries fit one block's staging buffer.
+struct CsrView {
+    int64_t nrows = 0, nnz = 0, nblk = 0;
+    const int64_t *rowptr = nullptr;
+    const int32_t *col = nullptr;
+    const int32_t *blk = nullptr;
+};
+
+constexpr int STREAM_CAP = 2048;   // entries per row block (8 per thread of 256)
+// Row-block boundaries for the block-streamed kernels; throws if a row is longer
+// than STREAM_CAP.
+std::vector<int32_t> row_blocks(const int64_t *rowptr, int64_t nrows);
+
 struct DevCsr {
     int64_t nrows = 0, ncols = 0, nnz = 0;
     DArray<int64_t> rowptr;
     DArray<int32_t> col;
+    DArray<int32_t> blk;
+    int64_t nblk = 0;
     DArray<double> val64;
     DArray<float> val32;
     void upload(const Csr &h, bool fp32, hipStream_t s);
+    CsrView view() const {
+        CsrView v;
+        v.nrows = nrows;
+        v.nnz = nnz;
+        v.nblk = nblk;
+        v.rowptr = rowptr.p;
+        v.col = col.p;
+        v.blk = blk.p;
+        return v;
+    }
 };
 
 struct Level {
@@ -231,22 +257,19 @@ void scaling_from_diag(int64_t N, const double *vals, const int64_t *diag_pos, d
 void gather(int64_t n, const double *src, const int64_t *map, double *dst, hipStream_t s);
 void scale_vec(int64_t n, const double *x, const double *sc, double *y, int invert, hipStream_t s);
 
-// sparse and dense linear algebra
+// sparse and dense linear algebra (block-streamed CSR)
 template <typename TM, typename TX, typename TY>
-void spmv(int64_t nrows, const int64_t *rowptr, const int32_t *col, const TM *val, const TX *x, TY *y,
-          int64_t nnz, hipStream_t s);
+void spmv(const CsrView &A, const TM *val, const TX *x, TY *y, hipStream_t s);
 // y = b - A x
 template <typename T>
-void residual(int64_t n, const int64_t *rowptr, const int32_t *col, const T *val, const T *x, const T *b,
-              T *y, int64_t nnz, hipStream_t s);
-// Chebyshev step: x_out = x_in + d_new, d_new = c1 d + c2 (b - A x_in)  (first: x_in may be null => x_in = 0)
+void residual(const CsrView &A, const T *val, const T *x, const T *b, T *y, hipStream_t s);
+// Chebyshev step: x_out = x_in + d_new, d_new = c1 d + c2 (b - A x_in)  (x_in null => x_in = 0)
 template <typename T>
-void cheb_step(int64_t n, const int64_t *rowptr, const int32_t *col, const T *val, const T *x_in,
-               const T *b, T *d, T *x_out, double c1, double c2, int64_t nnz, hipStream_t s);
+void cheb_step(const CsrView &A, const T *val, const T *x_in, const T *b, T *d, T *x_out, double c1,
+               double c2, hipStream_t s);
 // x += P xc
 template <typename T>
-void prolong_add(int64_t n, const int64_t *rowptr, const int32_t *col, const T *val, const T *xc, T *x,
-                 int64_t nnz, hipStream_t s);
+void prolong_add(const CsrView &P, const T *val, const T *xc, T *x, hipStream_t s);
 template <typename TA, typename TB>
 void convert(int64_t n, const TA *a, TB *b, hipStream_t s);
 void coarse_solve(int64_t n, const int32_t *comp, const int32_t *cloc, const int32_t *cmem, const int64_t *cstart,

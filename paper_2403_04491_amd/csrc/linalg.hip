@@ -3,11 +3,9 @@
 // dense solve, and the Krylov vector kernels with deterministic two-stage
 // reductions (classical Gram-Schmidt multi-dot and update, norms, axpys).
 //
-// SpMV maps a group of G lanes (G = 4..32, chosen from the mean row length) to
-// one CSR row: the group streams the row's column indices and values with
-// consecutive addresses and reduces its partial sums with cross-lane shuffles
-// inside the 64-wide wavefront.  All work is HBM-bound; nothing here is a dense
-// contraction, so no matrix-core instructions are involved.
+// SpMV streams blocks of whole rows (see stream_rows).  All work is HBM-bound;
+// nothing here is a dense contraction, so no matrix-core instructions are
+// involved.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -42,71 +40,129 @@ __device__ inline T ldg_stream(const T *p) {
     return __builtin_nontemporal_load(p);
 }
 
-template <int G, typename TM, typename TX, typename A>
-__device__ inline A row_dot(int64_t row, int lane, const int64_t *__restrict__ rowptr,
-                            const int32_t *__restrict__ col, const TM *__restrict__ val,
-                            const TX *__restrict__ x) {
-    const int64_t k0 = rowptr[row], k1 = rowptr[row + 1];
-    A s = A(0);
-    for (int64_t k = k0 + lane; k < k1; k += G) s += A(ldg_stream(val + k)) * A(x[ldg_stream(col + k)]);
-    return group_sum<G>(s);
-}
-
-template <int G, typename TM, typename TX, typename TY>
-__global__ void __launch_bounds__(TPB) k_spmv(int64_t nrows, const int64_t *__restrict__ rowptr,
-                                              const int32_t *__restrict__ col, const TM *__restrict__ val,
-                                              const TX *__restrict__ x, TY *__restrict__ y) {
-    using A = typename Acc<TM>::type;
-    const int64_t row = (int64_t(blockIdx.x) * TPB + threadIdx.x) / G;
-    const int lane = threadIdx.x % G;
-    if (row >= nrows) return;
-    const A s = row_dot<G, TM, TX, A>(row, lane, rowptr, col, val, x);
-    if (lane == 0) y[row] = TY(s);
-}
-
-template <int G, typename T>
-__global__ void __launch_bounds__(TPB) k_residual(int64_t nrows, const int64_t *__restrict__ rowptr,
-                                                  const int32_t *__restrict__ col, const T *__restrict__ val,
-                                                  const T *__restrict__ x, const T *__restrict__ b,
-                                                  T *__restrict__ y) {
-    using A = typename Acc<T>::type;
-    const int64_t row = (int64_t(blockIdx.x) * TPB + threadIdx.x) / G;
-    const int lane = threadIdx.x % G;
-    if (row >= nrows) return;
-    const A s = row_dot<G, T, T, A>(row, lane, rowptr, col, val, x);
-    if (lane == 0) y[row] = T(A(b[row]) - s);
-}
-
-// d <- c1 d + c2 (b - A x_in);  x_out <- x_in + d.   x_in == nullptr means x_in = 0.
-template <int G, typename T>
-__global__ void __launch_bounds__(TPB) k_cheb(int64_t nrows, const int64_t *__restrict__ rowptr,
-                                              const int32_t *__restrict__ col, const T *__restrict__ val,
-                                              const T *__restrict__ xin, const T *__restrict__ b,
-                                              T *__restrict__ d, T *__restrict__ xout, double c1, double c2) {
-    using A = typename Acc<T>::type;
-    const int64_t row = (int64_t(blockIdx.x) * TPB + threadIdx.x) / G;
-    const int lane = threadIdx.x % G;
-    if (row >= nrows) return;
-    A ax = A(0);
-    if (xin) ax = row_dot<G, T, T, A>(row, lane, rowptr, col, val, xin);
-    if (lane == 0) {
-        const A r = A(b[row]) - ax;
-        const A dn = (c1 == 0.0 ? A(0) : A(c1) * A(d[row])) + A(c2) * r;
-        d[row] = T(dn);
-        xout[row] = T((xin ? A(xin[row]) : A(0)) + dn);
+// ---------------------------------------------------------------- block-streamed CSR
+// Block b owns rows blk[b]..blk[b+1]-1, whose entries (at most STREAM_CAP) are
+// contiguous in col/val.  Phase 1: the 256 threads stream the block's column
+// indices and values with unit-stride loads (8 per thread, all issued before
+// any x gather so the gathers overlap), multiply by the gathered x and stage
+// the products in LDS.  Phase 2: each row is summed from LDS in a fixed order
+// by one thread and handed to the epilogue (plain store, residual, Chebyshev
+// update, prolongation add).  Deterministic: no atomics, fixed summation order.
+template <typename TM, typename TX, typename A, class Epi>
+__device__ inline void stream_rows(const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+                                   const TM *__restrict__ val, const TX *__restrict__ x,
+                                   const int32_t *__restrict__ blk, Epi &epi) {
+    constexpr int PER = STREAM_CAP / TPB;
+    __shared__ A prod[STREAM_CAP];
+    const int32_t r0 = blk[blockIdx.x], r1 = blk[blockIdx.x + 1];
+    const int64_t k0 = rowptr[r0];
+    const int n = int(rowptr[r1] - k0);
+    int32_t c[PER];
+    TM v[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int i = threadIdx.x + u * TPB;
+        if (i < n) {
+            c[u] = __builtin_nontemporal_load(col + k0 + i);
+            v[u] = __builtin_nontemporal_load(val + k0 + i);
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int i = threadIdx.x + u * TPB;
+        if (i < n) prod[i] = A(v[u]) * A(x[c[u]]);
+    }
+    __syncthreads();
+    for (int32_t row = r0 + int32_t(threadIdx.x); row < r1; row += TPB) {
+        const int a = int(rowptr[row] - k0), b = int(rowptr[row + 1] - k0);
+        A sum = A(0);
+        for (int k = a; k < b; ++k) sum += prod[k];
+        epi(row, sum);
     }
 }
 
-template <int G, typename T>
-__global__ void __launch_bounds__(TPB) k_prolong_add(int64_t nrows, const int64_t *__restrict__ rowptr,
-                                                     const int32_t *__restrict__ col, const T *__restrict__ val,
-                                                     const T *__restrict__ xc, T *__restrict__ x) {
+template <typename TY, typename A>
+struct EpiStore {
+    TY *y;
+    __device__ void operator()(int32_t row, A s) const { y[row] = TY(s); }
+};
+
+template <typename T, typename A>
+struct EpiResidual {
+    const T *b;
+    T *y;
+    __device__ void operator()(int32_t row, A s) const { y[row] = T(A(b[row]) - s); }
+};
+
+template <typename T, typename A>
+struct EpiCheb {
+    const T *xin, *b;
+    T *d, *xout;
+    A c1, c2;
+    bool use_d;
+    __device__ void operator()(int32_t row, A s) const {
+        const A r = A(b[row]) - s;
+        const A dn = (use_d ? c1 * A(d[row]) : A(0)) + c2 * r;
+        d[row] = T(dn);
+        xout[row] = T(A(xin[row]) + dn);
+    }
+};
+
+template <typename T, typename A>
+struct EpiAdd {
+    T *x;
+    __device__ void operator()(int32_t row, A s) const { x[row] = T(A(x[row]) + s); }
+};
+
+template <typename TM, typename TX, typename TY>
+__global__ void __launch_bounds__(TPB) k_spmv(const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+                                              const TM *__restrict__ val, const TX *__restrict__ x,
+                                              const int32_t *__restrict__ blk, TY *__restrict__ y) {
+    using A = typename Acc<TM>::type;
+    EpiStore<TY, A> e{y};
+    stream_rows<TM, TX, A>(rowptr, col, val, x, blk, e);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_residual(const int64_t *__restrict__ rowptr,
+                                                  const int32_t *__restrict__ col, const T *__restrict__ val,
+                                                  const T *__restrict__ x, const int32_t *__restrict__ blk,
+                                                  const T *__restrict__ b, T *__restrict__ y) {
     using A = typename Acc<T>::type;
-    const int64_t row = (int64_t(blockIdx.x) * TPB + threadIdx.x) / G;
-    const int lane = threadIdx.x % G;
-    if (row >= nrows) return;
-    const A s = row_dot<G, T, T, A>(row, lane, rowptr, col, val, xc);
-    if (lane == 0) x[row] = T(A(x[row]) + s);
+    EpiResidual<T, A> e{b, y};
+    stream_rows<T, T, A>(rowptr, col, val, x, blk, e);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_cheb(const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+                                              const T *__restrict__ val, const T *__restrict__ xin,
+                                              const int32_t *__restrict__ blk, const T *__restrict__ b,
+                                              T *__restrict__ d, T *__restrict__ xout, double c1, double c2) {
+    using A = typename Acc<T>::type;
+    EpiCheb<T, A> e{xin, b, d, xout, A(c1), A(c2), c1 != 0.0};
+    stream_rows<T, T, A>(rowptr, col, val, xin, blk, e);
+}
+
+// first Chebyshev step from x = 0: d = c2 b, x = d (no operator application)
+template <typename T>
+__global__ void k_cheb_first(int64_t n, const T *__restrict__ b, T *__restrict__ d, T *__restrict__ xout,
+                             double c2) {
+    using A = typename Acc<T>::type;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
+        const T v = T(A(c2) * A(b[i]));
+        d[i] = v;
+        xout[i] = v;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_prolong_add(const int64_t *__restrict__ rowptr,
+                                                     const int32_t *__restrict__ col, const T *__restrict__ val,
+                                                     const T *__restrict__ xc, const int32_t *__restrict__ blk,
+                                                     T *__restrict__ x) {
+    using A = typename Acc<T>::type;
+    EpiAdd<T, A> e{x};
+    stream_rows<T, T, A>(rowptr, col, val, xc, blk, e);
 }
 
 template <typename TA, typename TB>
@@ -246,23 +302,6 @@ inline unsigned stream_grid(int64_t n) {
     return unsigned(g);
 }
 
-// group width from the mean row length
-inline int pick_group(int64_t nrows, int64_t nnz) {
-    const double avg = nrows ? double(nnz) / double(nrows) : 0.0;
-    if (avg <= 6.0) return 4;
-    if (avg <= 20.0) return 8;
-    if (avg <= 48.0) return 16;
-    return 32;
-}
-
-#define KNP_DISPATCH_G(G_, ...)                              \
-    switch (G_) {                                            \
-        case 4: { constexpr int G = 4; __VA_ARGS__; } break;   \
-        case 8: { constexpr int G = 8; __VA_ARGS__; } break;   \
-        case 16: { constexpr int G = 16; __VA_ARGS__; } break; \
-        default: { constexpr int G = 32; __VA_ARGS__; } break; \
-    }
-
 }  // namespace
 
 int reduce_blocks(int64_t n) {
@@ -273,39 +312,36 @@ int reduce_blocks(int64_t n) {
 }
 
 template <typename TM, typename TX, typename TY>
-void spmv(int64_t nrows, const int64_t *rowptr, const int32_t *col, const TM *val, const TX *x, TY *y,
-          int64_t nnz, hipStream_t s) {
-    if (nrows == 0) return;
-    const int g = pick_group(nrows, nnz);
-    KNP_DISPATCH_G(g, hipLaunchKernelGGL((k_spmv<G, TM, TX, TY>), dim3(grid_for(nrows * G, TPB)), dim3(TPB), 0, s,
-                                         nrows, rowptr, col, val, x, y));
+void spmv(const CsrView &A, const TM *val, const TX *x, TY *y, hipStream_t s) {
+    if (A.nblk == 0) return;
+    hipLaunchKernelGGL((k_spmv<TM, TX, TY>), dim3(unsigned(A.nblk)), dim3(TPB), 0, s, A.rowptr, A.col, val, x, A.blk,
+                       y);
 }
 
 template <typename T>
-void residual(int64_t n, const int64_t *rowptr, const int32_t *col, const T *val, const T *x, const T *b, T *y,
-              int64_t nnz, hipStream_t s) {
-    if (n == 0) return;
-    const int g = pick_group(n, nnz);
-    KNP_DISPATCH_G(g, hipLaunchKernelGGL((k_residual<G, T>), dim3(grid_for(n * G, TPB)), dim3(TPB), 0, s, n, rowptr,
-                                         col, val, x, b, y));
+void residual(const CsrView &A, const T *val, const T *x, const T *b, T *y, hipStream_t s) {
+    if (A.nblk == 0) return;
+    hipLaunchKernelGGL((k_residual<T>), dim3(unsigned(A.nblk)), dim3(TPB), 0, s, A.rowptr, A.col, val, x, A.blk, b,
+                       y);
 }
 
 template <typename T>
-void cheb_step(int64_t n, const int64_t *rowptr, const int32_t *col, const T *val, const T *x_in, const T *b, T *d,
-               T *x_out, double c1, double c2, int64_t nnz, hipStream_t s) {
-    if (n == 0) return;
-    const int g = pick_group(n, nnz);
-    KNP_DISPATCH_G(g, hipLaunchKernelGGL((k_cheb<G, T>), dim3(grid_for(n * G, TPB)), dim3(TPB), 0, s, n, rowptr,
-                                         col, val, x_in, b, d, x_out, c1, c2));
+void cheb_step(const CsrView &A, const T *val, const T *x_in, const T *b, T *d, T *x_out, double c1, double c2,
+               hipStream_t s) {
+    if (A.nrows == 0) return;
+    if (!x_in) {
+        hipLaunchKernelGGL((k_cheb_first<T>), dim3(stream_grid(A.nrows)), dim3(TPB), 0, s, A.nrows, b, d, x_out, c2);
+        return;
+    }
+    hipLaunchKernelGGL((k_cheb<T>), dim3(unsigned(A.nblk)), dim3(TPB), 0, s, A.rowptr, A.col, val, x_in, A.blk, b, d,
+                       x_out, c1, c2);
 }
 
 template <typename T>
-void prolong_add(int64_t n, const int64_t *rowptr, const int32_t *col, const T *val, const T *xc, T *x, int64_t nnz,
-                 hipStream_t s) {
-    if (n == 0) return;
-    const int g = pick_group(n, nnz);
-    KNP_DISPATCH_G(g, hipLaunchKernelGGL((k_prolong_add<G, T>), dim3(grid_for(n * G, TPB)), dim3(TPB), 0, s, n,
-                                         rowptr, col, val, xc, x));
+void prolong_add(const CsrView &P, const T *val, const T *xc, T *x, hipStream_t s) {
+    if (P.nblk == 0) return;
+    hipLaunchKernelGGL((k_prolong_add<T>), dim3(unsigned(P.nblk)), dim3(TPB), 0, s, P.rowptr, P.col, val, xc, P.blk,
+                       x);
 }
 
 template <typename TA, typename TB>
@@ -369,24 +405,18 @@ void sub(int64_t n, const double *a, const double *b, double *y, hipStream_t s) 
 }
 
 // explicit instantiations
-template void spmv<double, double, double>(int64_t, const int64_t *, const int32_t *, const double *,
-                                           const double *, double *, int64_t, hipStream_t);
-template void spmv<double, float, double>(int64_t, const int64_t *, const int32_t *, const double *, const float *,
-                                          double *, int64_t, hipStream_t);
-template void spmv<float, float, float>(int64_t, const int64_t *, const int32_t *, const float *, const float *,
-                                        float *, int64_t, hipStream_t);
-template void residual<double>(int64_t, const int64_t *, const int32_t *, const double *, const double *,
-                               const double *, double *, int64_t, hipStream_t);
-template void residual<float>(int64_t, const int64_t *, const int32_t *, const float *, const float *, const float *,
-                              float *, int64_t, hipStream_t);
-template void cheb_step<double>(int64_t, const int64_t *, const int32_t *, const double *, const double *,
-                                const double *, double *, double *, double, double, int64_t, hipStream_t);
-template void cheb_step<float>(int64_t, const int64_t *, const int32_t *, const float *, const float *, const float *,
-                               float *, float *, double, double, int64_t, hipStream_t);
-template void prolong_add<double>(int64_t, const int64_t *, const int32_t *, const double *, const double *, double *,
-                                  int64_t, hipStream_t);
-template void prolong_add<float>(int64_t, const int64_t *, const int32_t *, const float *, const float *, float *,
-                                 int64_t, hipStream_t);
+template void spmv<double, double, double>(const CsrView &, const double *, const double *, double *, hipStream_t);
+template void spmv<double, float, double>(const CsrView &, const double *, const float *, double *, hipStream_t);
+template void spmv<float, float, float>(const CsrView &, const float *, const float *, float *, hipStream_t);
+template void residual<double>(const CsrView &, const double *, const double *, const double *, double *,
+                               hipStream_t);
+template void residual<float>(const CsrView &, const float *, const float *, const float *, float *, hipStream_t);
+template void cheb_step<double>(const CsrView &, const double *, const double *, const double *, double *, double *,
+                                double, double, hipStream_t);
+template void cheb_step<float>(const CsrView &, const float *, const float *, const float *, float *, float *, double,
+                               double, hipStream_t);
+template void prolong_add<double>(const CsrView &, const double *, const double *, double *, hipStream_t);
+template void prolong_add<float>(const CsrView &, const float *, const float *, float *, hipStream_t);
 template void convert<double, float>(int64_t, const double *, float *, hipStream_t);
 template void convert<float, double>(int64_t, const float *, double *, hipStream_t);
 template void convert<double, double>(int64_t, const double *, double *, hipStream_t);

@@ -51,9 +51,9 @@ void apply_operator(knp_ctx *c, bool transpose, const double *x, double *y) {
     const int64_t N = c->hm.N;
     hipEvent_t t0 = c->tm.begin(KNP_TIMER_SPMV_A, c->stream);
     if (transpose)
-        launch::spmv<double, double, double>(N, c->d_rowptrT.p, c->d_colT.p, c->d_valsT.p, x, y, c->hm.nnz, c->stream);
+        launch::spmv<double, double, double>(c->viewT(), c->d_valsT.p, x, y, c->stream);
     else
-        launch::spmv<double, double, double>(N, c->d_rowptr.p, c->d_colidx.p, c->d_vals.p, x, y, c->hm.nnz, c->stream);
+        launch::spmv<double, double, double>(c->viewA(), c->d_vals.p, x, y, c->stream);
     c->tm.end(KNP_TIMER_SPMV_A, t0, 12.0 * double(c->hm.nnz) + 32.0 * double(N) + 8.0, c->stream);
 }
 
@@ -109,10 +109,8 @@ knp_status krylov_solve(knp_ctx *c, bool transpose, const double *b, double *x, 
                     float *zj = c->Z32.p + size_t(j) * N;
                     amg_vcycle(c->amg, vj, zj, s, &c->tm);
                     hipEvent_t t0 = c->tm.begin(KNP_TIMER_SPMV_A, s);
-                    launch::spmv<double, float, double>(N, transpose ? c->d_rowptrT.p : c->d_rowptr.p,
-                                                        transpose ? c->d_colT.p : c->d_colidx.p,
-                                                        transpose ? c->d_valsT.p : c->d_vals.p, zj, wj, c->hm.nnz,
-                                                        s);
+                    launch::spmv<double, float, double>(transpose ? c->viewT() : c->viewA(),
+                                                        transpose ? c->d_valsT.p : c->d_vals.p, zj, wj, s);
                     c->tm.end(KNP_TIMER_SPMV_A, t0, 12.0 * double(c->hm.nnz) + 28.0 * double(N) + 8.0, s);
                 } else {
                     double *zj = c->Z64.p + size_t(j) * N;
@@ -213,6 +211,12 @@ void ensure_transpose(knp_ctx *c) {
         c->d_colT.upload(colT, s);
         c->d_permT.alloc(m.nnz);
         c->d_permT.upload(perm, s);
+        {
+            std::vector<int32_t> b = row_blocks(rpT.data(), m.N);
+            c->nblkT = int64_t(b.size()) - 1;
+            c->d_blkT.alloc(b.size());
+            c->d_blkT.upload(b, s);
+        }
         c->d_valsT.alloc(m.nnz);
         hip_check(hipStreamSynchronize(s), "transpose upload");
         c->have_T = true;
