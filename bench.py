@@ -122,6 +122,43 @@ def cpu_baseline(per_pitch, n_steps, log):
             "threads_env": {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS")}}
 
 
+def kernels_only(solver, args, amg_kw, log):
+    """Operator applications only (for counter collection), on the workload's
+    first-step matrix and hierarchy."""
+    import torch
+    from paper_2403_04491_amd import amg_opts
+    prec = 1 if args.precision == "fp32" else 0
+    solver.amg_opts = amg_opts(precision=prec, **amg_kw)
+    solver.assemble(1)
+    torch.cuda.synchronize()
+    N = solver.info.N
+    gen = torch.Generator(device=solver.dev).manual_seed(0)
+    x = torch.rand(N, dtype=torch.float64, device=solver.dev, generator=gen)
+    y = torch.empty_like(x)
+    # calibration copy: exactly 1 GiB read + 1 GiB written
+    a = torch.ones(2 ** 27, dtype=torch.float64, device=solver.dev)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    solver.ctx.timing(True)
+    t0 = time.perf_counter()
+    for _ in range(args.reps):
+        solver.ctx.apply(0, x, y)
+        solver.ctx.apply(1, x, y)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    timers = solver.ctx.timing_read()
+    solver.ctx.timing(False)
+    kernel, roof = roofline_of(timers)
+    out = {"mode": "kernels-only", "precision": "fp32_amg" if prec else "fp64", "reps": args.reps,
+           "N": N, "nnz_A": solver.info.nnz_A, "wall_s": round(el, 3),
+           "kernel_gbs": {n: round(t["bytes"] / (t["total_ms"] * 1e-3) / 1e9, 1)
+                          for n, t in timers.items() if t["launches"] and t["bytes"] > 0},
+           "timers": timers, "roofline": roof, "calibration_copy_bytes": 2 * 8 * 2 ** 27}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -139,6 +176,10 @@ def main():
     ap.add_argument("--cheb-ratio", type=float, default=10.0)
     ap.add_argument("--strength", type=float, default=0.25)
     ap.add_argument("--coarse-max", type=int, default=2000)
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="profiling mode: apply S A S and one V-cycle --reps times after setup, plus a "
+                         "1 GiB device copy that calibrates the HBM byte counters")
+    ap.add_argument("--reps", type=int, default=10)
     ap.add_argument("--quiet", action="store_true")
     args = ap.parse_args()
 
@@ -168,6 +209,9 @@ def main():
     t_upload = time.perf_counter() - t0
     info = solver.info
     log(f"mesh upload {t_upload:.1f} s: N={info.N} nnz(A)={info.nnz_A} nnz(P0)={info.nnz_P0}")
+    if args.kernels_only:
+        kernels_only(solver, args, amg_kw, log)
+        return
     u0 = solver.u.clone()
     g0 = solver.gates.clone()
     runs = {}
