@@ -73,7 +73,9 @@ def run_precision(solver, u0, g0, precision, warmup, steps, log, first_restart, 
     timers = solver.ctx.timing_read()
     solver.ctx.timing(False)
     log(f"  timed {steps} steps in {elapsed:.3f} s, its={its}")
-    return {"steps_per_s": steps / elapsed, "ms_per_step": 1e3 * elapsed / steps, "its": its,
+    hier = solver.ctx.amg_stats()
+    log(f"  hierarchy rows {hier['rows']} nnz {hier['nnz']}")
+    return {"hierarchy": hier, "steps_per_s": steps / elapsed, "ms_per_step": 1e3 * elapsed / steps, "its": its,
             "its_warmup": its_w, "amg_setup_s": setup_s, "timers": timers,
             "u": solver.u.cpu().numpy()}
 
@@ -172,8 +174,8 @@ def main():
     ap.add_argument("--first-restart", type=int, default=200,
                     help="FGMRES restart of the untimed first step (later steps: 30)")
     ap.add_argument("--restart", type=int, default=30)
-    ap.add_argument("--cheb-degree", type=int, default=2)
-    ap.add_argument("--cheb-ratio", type=float, default=10.0)
+    ap.add_argument("--cheb-degree", type=int, default=3)
+    ap.add_argument("--cheb-ratio", type=float, default=2.5)
     ap.add_argument("--strength", type=float, default=0.25)
     ap.add_argument("--coarse-max", type=int, default=2000)
     ap.add_argument("--kernels-only", action="store_true",
@@ -250,6 +252,9 @@ def main():
         "its_per_step": {k: float(sum(r["its"]) / len(r["its"])) for k, r in runs.items()},
         "steps_per_s": {k: round(r["steps_per_s"], 3) for k, r in runs.items()},
         "ms_per_step_by_precision": {k: round(r["ms_per_step"], 2) for k, r in runs.items()},
+        "amg_hierarchy": {k: r["hierarchy"] for k, r in runs.items()},
+        "operator_complexity": {k: round(sum(r["hierarchy"]["nnz"]) / r["hierarchy"]["nnz"][0], 3)
+                                for k, r in runs.items()},
         "setup_s": {"mesh_upload": round(t_upload, 2),
                     **{f"amg_setup_{k}": round(r["amg_setup_s"], 2) for k, r in runs.items()}},
         "kernel_gbs": {k: {n: round(t["bytes"] / (t["total_ms"] * 1e-3) / 1e9, 1)

@@ -161,9 +161,13 @@ knp_status knp_assemble_step(knp_ctx *ctx, double t_n, double dt, const double *
 
 /* Build the algebraic-multigrid hierarchy of P_0 (eq. ``P_prec``), frozen for all
  * steps (same section).  Must follow the first knp_assemble_step (else
- * KNP_E_STATE).  opts NULL = defaults (FP64, strength 0.25, Chebyshev degree 2 on
- * [lmax/10, lmax], coarse_max 2000, max_levels 20). */
+ * KNP_E_STATE).  opts NULL = defaults (FP64, strength 0.25, Chebyshev degree 3 on
+ * [lmax/2.5, lmax], coarse_max 2000, max_levels 20). */
 knp_status knp_amg_setup(knp_ctx *ctx, const knp_amg_opts *opts);
+
+/* Shape of the hierarchy built by knp_amg_setup: number of levels (<= 32) and,
+ * per level, rows and stored nonzeros of the level operator (host arrays of 32). */
+knp_status knp_amg_stats(knp_ctx *ctx, int32_t *n_levels, int64_t *level_rows, int64_t *level_nnz);
 
 /* Solve A_{n-1} x = b with right-preconditioned flexible GMRES(restart) (the
  * paper's GMRES with one V-cycle of AMG(P_0) per iteration).  b: device [N]

@@ -609,7 +609,7 @@ struct LV<float> {
 // V-cycle on level l: solves approximately A_l x = b, with b and the result in
 // the level's own buffers; returns the buffer holding x.
 template <typename T>
-T *vcycle_level(Amg &amg, size_t l, const T *b, hipStream_t s, Timers *tm) {
+T *vcycle_level(Amg &amg, size_t l, const T *b, hipStream_t s, Timers *tm, T *out = nullptr) {
     Level *L = amg.levels[l];
     if (l + 1 == amg.levels.size()) {
         T *x = LV<T>::x(L);
@@ -657,10 +657,12 @@ T *vcycle_level(Amg &amg, size_t l, const T *b, hipStream_t s, Timers *tm) {
     launch::spmv<T, T, T>(L->R.view(), LV<T>::R(L), t, bc, s);
     T *xc = vcycle_level<T>(amg, l + 1, bc, s, tm);
     launch::prolong_add<T>(L->P.view(), LV<T>::P(L), xc, x, s);
-    // post-smoothing
+    // post-smoothing; the last step writes to `out` when given
     for (size_t k = 0; k < cc.size(); ++k) {
-        cheb(x, x2, cc[k].first, cc[k].second);
-        std::swap(x, x2);
+        T *dst = (out && k + 1 == cc.size()) ? out : x2;
+        cheb(x, dst, cc[k].first, cc[k].second);
+        x2 = x;
+        x = dst;
     }
     return x;
 }
@@ -673,11 +675,13 @@ void amg_vcycle(Amg &amg, const double *v, void *z, hipStream_t s, Timers *tm) {
     hipEvent_t e = tm ? tm->begin(KNP_TIMER_VCYCLE, s) : nullptr;
     if (amg.fp32) {
         launch::convert<double, float>(n, v, L0->b32.p, s);
-        float *x = vcycle_level<float>(amg, 0, L0->b32.p, s, tm);
-        hip_check(hipMemcpyAsync(z, x, size_t(n) * sizeof(float), hipMemcpyDeviceToDevice, s), "vcycle copy");
+        float *zf = static_cast<float *>(z);
+        float *x = vcycle_level<float>(amg, 0, L0->b32.p, s, tm, zf);
+        if (x != zf) hip_check(hipMemcpyAsync(z, x, size_t(n) * sizeof(float), hipMemcpyDeviceToDevice, s), "copy");
     } else {
-        double *x = vcycle_level<double>(amg, 0, v, s, tm);
-        hip_check(hipMemcpyAsync(z, x, size_t(n) * sizeof(double), hipMemcpyDeviceToDevice, s), "vcycle copy");
+        double *zd = static_cast<double *>(z);
+        double *x = vcycle_level<double>(amg, 0, v, s, tm, zd);
+        if (x != zd) hip_check(hipMemcpyAsync(z, x, size_t(n) * sizeof(double), hipMemcpyDeviceToDevice, s), "copy");
     }
     if (tm) tm->end(KNP_TIMER_VCYCLE, e, 0.0, s);
 }

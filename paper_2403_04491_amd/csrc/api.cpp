@@ -492,7 +492,7 @@ knp_status knp_amg_setup(knp_ctx *c, const knp_amg_opts *opts) {
     return guarded(c, [&]() -> knp_status {
         need_device(c);
         if (!c->assembled) return fail(c, KNP_E_STATE, "knp_assemble_step must come first");
-        knp_amg_opts o{0, 0.25, 2, 10.0, 2000, 20};
+        knp_amg_opts o{0, 0.25, 3, 2.5, 2000, 20};
         if (opts) o = *opts;
         if (o.precision != 0 && o.precision != 1) return fail(c, KNP_E_ARG, "precision must be 0 or 1");
         if (!(o.strength > 0.0 && o.strength < 1.0) || o.cheb_degree < 1 || !(o.cheb_ratio > 1.0) ||
@@ -501,6 +501,20 @@ knp_status knp_amg_setup(knp_ctx *c, const knp_amg_opts *opts) {
         hip_check(hipSetDevice(c->device), "set device");
         amg_build(c->amg, c->hm, c->p0_vals, c->near_null, o, c->stream);
         c->m_alloc = -1;   // Z precision may change
+        return KNP_OK;
+    });
+}
+
+knp_status knp_amg_stats(knp_ctx *c, int32_t *n_levels, int64_t *level_rows, int64_t *level_nnz) {
+    return guarded(c, [&]() -> knp_status {
+        if (!c->amg.ready) return fail(c, KNP_E_STATE, "knp_amg_setup has not been called");
+        if (!n_levels || !level_rows || !level_nnz) return fail(c, KNP_E_ARG, "NULL output");
+        const size_t L = std::min<size_t>(32, c->amg.level_n.size());
+        *n_levels = int32_t(L);
+        for (size_t l = 0; l < L; ++l) {
+            level_rows[l] = c->amg.level_n[l];
+            level_nnz[l] = c->amg.level_nnz[l];
+        }
         return KNP_OK;
     });
 }

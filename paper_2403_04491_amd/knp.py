@@ -21,7 +21,7 @@ KNP_E_NOCONV = 5
 EXPORTS = ["knp_create", "knp_destroy", "knp_last_error", "knp_mesh_upload", "knp_get_layout",
            "knp_get_gamma", "knp_set_params", "knp_assemble_step", "knp_amg_setup",
            "knp_gmres_solve", "knp_adjoint_solve", "knp_step_vjp", "knp_apply",
-           "knp_get_scaling", "knp_get_values", "knp_timing", "knp_timing_read"]
+           "knp_get_scaling", "knp_get_values", "knp_timing", "knp_timing_read", "knp_amg_stats"]
 TIMERS = ["spmv_A", "cheb_L0", "resid_L0", "vcycle", "assembly"]
 
 
@@ -89,6 +89,7 @@ def load_library(path: str = _LIB_PATH) -> C.CDLL:
     lib.knp_get_scaling.argtypes = [P, P]
     lib.knp_get_values.argtypes = [P, P]
     lib.knp_timing.argtypes = [P, C.c_int]
+    lib.knp_amg_stats.argtypes = [P, P, P, P]
     lib.knp_timing_read.argtypes = [P, P]
     for name in EXPORTS:
         if name not in ("knp_destroy", "knp_last_error"):
@@ -125,7 +126,7 @@ def _hptr(a):
     return a.ctypes.data_as(C.c_void_p)
 
 
-def amg_opts(precision=0, strength=0.25, cheb_degree=2, cheb_ratio=10.0, coarse_max=2000, max_levels=20):
+def amg_opts(precision=0, strength=0.25, cheb_degree=3, cheb_ratio=2.5, coarse_max=2000, max_levels=20):
     return AmgOpts(precision, strength, cheb_degree, cheb_ratio, coarse_max, max_levels)
 
 
@@ -255,6 +256,13 @@ class Context:
     def get_scaling(self, out):
         import torch
         self._check(self._lib.knp_get_scaling(self._c, _dptr(out, torch.float64, self.info.N)))
+
+    def amg_stats(self):
+        nl = C.c_int32()
+        rows = np.zeros(32, np.int64)
+        nnz = np.zeros(32, np.int64)
+        self._check(self._lib.knp_amg_stats(self._c, C.byref(nl), _hptr(rows), _hptr(nnz)))
+        return {"rows": rows[:nl.value].tolist(), "nnz": nnz[:nl.value].tolist()}
 
     def timing(self, enable: bool):
         self._check(self._lib.knp_timing(self._c, 1 if enable else 0))
