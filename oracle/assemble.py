@@ -203,10 +203,11 @@ def membrane_terms(case, lay: Layout, u_prev, gates, t, dt, theta=None) -> Membr
         gcond[hh, 1] += p["gbar_K"] * n_ ** 4
     I = gcond * (phiM[:, None] - E)
 
-    alpha = np.empty((2,) + ci.shape)
+    dtype = np.result_type(ci, ce, phiM, I)          # complex under complex-step perturbation
+    alpha = np.empty((2,) + ci.shape, dtype=dtype)
     C = np.empty_like(alpha)
     g = np.empty_like(alpha)
-    h = np.empty((2, len(phiM)))
+    h = np.empty((2, len(phiM)), dtype=dtype)
     for r, (c, sgn) in enumerate(((ci, 1.0), (ce, -1.0))):
         wgt = D[None, :] * z[None, :] ** 2 * c
         alpha[r] = wgt / wgt.sum(axis=1, keepdims=True)
@@ -272,8 +273,9 @@ class Assembler:
             key = (rb, cb)
             blocks[key] = blocks[key] + M if key in blocks else M
 
-        nodal = np.zeros(lay.n_vert)
-        f = np.zeros(N)
+        dtype = np.result_type(u_prev, mem.C)
+        nodal = np.zeros(lay.n_vert, dtype=dtype)
+        f = np.zeros(N, dtype=dtype)
 
         def put_f(r, fld, val):
             s0 = lay.dof(r, fld, 0)
@@ -311,7 +313,7 @@ class Assembler:
             # right-hand side
             for k in range(3):
                 ck = u_prev[lay.dof(r, k, np.arange(Nr[r]))]
-                gk = np.zeros(Nr[r])
+                gk = np.zeros(Nr[r], dtype=dtype)
                 gk[lay.loc[r, lay.gamma]] = mem.g[r, :, k]
                 fk = M @ ck - MG_rr @ gk
                 if vol_source is not None:
@@ -319,7 +321,7 @@ class Assembler:
                 if gamma_source is not None:
                     fk = fk - MG_rr @ gamma_source[r, k, lay.verts[r]]
                 put_f(r, k, fk)
-            hr = np.zeros(Nr[r])
+            hr = np.zeros(Nr[r], dtype=dtype)
             hr[lay.loc[r, lay.gamma]] = mem.h[r]
             fphi = -(MG_rr @ hr)
             if vol_source is not None:

@@ -172,7 +172,7 @@ def embed(A: sp.spmatrix, rowptr, colidx) -> np.ndarray:
     N = len(rowptr) - 1
     A = A.tocoo()
     keys_pat = np.repeat(np.arange(N, dtype=np.int64), np.diff(rowptr)) * N + colidx
-    vals = np.zeros(len(colidx))
+    vals = np.zeros(len(colidx), dtype=A.dtype)
     keys = A.row.astype(np.int64) * N + A.col
     pos = np.searchsorted(keys_pat, keys)
     pos_c = np.minimum(pos, len(keys_pat) - 1)
