@@ -108,7 +108,10 @@ typedef struct {
 /* Create a context on HIP device `hip_device`, enqueuing on `hip_stream`
  * (a hipStream_t; NULL = the default stream).  hip_device = -1 creates a
  * host-only context in which only knp_mesh_upload, knp_get_layout and
- * knp_get_gamma work (for checks of the host-side mesh logic). */
+ * knp_get_gamma work (for checks of the host-side mesh logic).  On failure
+ * *out is NULL and knp_last_error(NULL) gives the reason (per host thread).
+ * The library must share the process's one HIP runtime with whatever owns the
+ * device memory passed to it (e.g. load it after the framework's runtime). */
 knp_status knp_create(knp_ctx **out, int hip_device, void *hip_stream);
 void knp_destroy(knp_ctx *ctx);
 const char *knp_last_error(const knp_ctx *ctx);
@@ -173,7 +176,11 @@ knp_status knp_amg_stats(knp_ctx *ctx, int32_t *n_levels, int64_t *level_rows, i
  * paper's GMRES with one V-cycle of AMG(P_0) per iteration).  b: device [N]
  * (unscaled, e.g. f_n); x: device [N], in: initial guess (u_{n-1}), out: the
  * solution.  opts NULL = rtol 1e-6, restart 30, max_it 2000, reorth 0, precond 1.
- * Blocks until done.  KNP_E_NOCONV if max_it was reached (x is the last iterate). */
+ * Blocks until done.  KNP_E_NOCONV if max_it was reached, or earlier if rtol
+ * lies below the attainable accuracy: 50 restarts in a row whose cycle ended
+ * on a converged recurrence estimate while the recomputed residual, over the
+ * 50, did not halve (x is the last iterate; info->rel_res says where it
+ * stalled). */
 knp_status knp_gmres_solve(knp_ctx *ctx, const double *b, double *x,
                            const knp_solve_opts *opts, knp_solve_info *info);
 
@@ -183,11 +190,14 @@ knp_status knp_adjoint_solve(knp_ctx *ctx, const double *rhs, double *lambda,
                              const knp_solve_opts *opts, knp_solve_info *info);
 
 /* Vector-Jacobian products of the step residual R = A(u_prev, theta) u_n -
- * f(u_prev, theta) for the assembled step: accumulates
+ * f(u_prev, theta) (eq. ``lin_sys``) for the discrete adjoint: accumulates
  *   u_prev_bar += (dR/du_prev)^T lambda_n   and   theta_bar += (dR/dtheta)^T lambda_n
- * (both device; theta_bar may be NULL).  Must follow knp_assemble_step of the
- * same step (same u_prev, gates and theta).  Passive-leak membranes only
- * (KNP_E_ARG if a Hodgkin-Huxley cell is present). */
+ * (device; theta_bar [n_cells] may be NULL).  u_prev enters through the
+ * concentration-weighted stiffness, the mass term of f and the nodal membrane
+ * coefficients; theta through the leak currents.  Uses t_n, dt and the theta
+ * pointer of the most recent knp_assemble_step, which must be the call for this
+ * step (same u_prev and theta; theta must still be valid).  Passive-leak
+ * membranes only (KNP_E_ARG if a Hodgkin-Huxley cell is present). */
 knp_status knp_step_vjp(knp_ctx *ctx, const double *u_prev, const double *u_n,
                         const double *lambda_n, double *u_prev_bar, double *theta_bar);
 

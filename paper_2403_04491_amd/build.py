@@ -13,7 +13,7 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libknp.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
-HIP_SOURCES = ["assemble.hip", "linalg.hip"]
+HIP_SOURCES = ["assemble.hip", "linalg.hip", "vjp.hip"]
 CPP_SOURCES = ["mesh.cpp", "amg.cpp", "solver.cpp", "api.cpp"]
 
 HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",

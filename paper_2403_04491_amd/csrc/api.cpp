@@ -206,29 +206,38 @@ void need_device(knp_ctx *c) {
 
 extern "C" {
 
+// Text of the last failed knp_create on this thread (no context exists to hold it).
+static thread_local std::string g_create_err = "no error";
+
+static knp_status create_failed(knp_ctx *c, knp_status st, std::string msg) {
+    delete c;
+    g_create_err = std::move(msg);
+    return st;
+}
+
 knp_status knp_create(knp_ctx **out, int hip_device, void *hip_stream) {
     if (!out) return KNP_E_ARG;
     *out = nullptr;
     knp_ctx *c = new (std::nothrow) knp_ctx();
-    if (!c) return KNP_E_NOMEM;
+    if (!c) return create_failed(nullptr, KNP_E_NOMEM, "out of host memory");
     c->device = hip_device;
     c->host_only = hip_device < 0;
     c->stream = static_cast<hipStream_t>(hip_stream);
     if (!c->host_only) {
         int n = 0;
-        if (hipGetDeviceCount(&n) != hipSuccess || hip_device >= n) {
-            delete c;
-            return KNP_E_HIP;
-        }
-        if (hipSetDevice(hip_device) != hipSuccess) {
-            delete c;
-            return KNP_E_HIP;
-        }
+        const hipError_t e = hipGetDeviceCount(&n);
+        if (e != hipSuccess)
+            return create_failed(c, KNP_E_HIP, std::string("hipGetDeviceCount: ") + hipGetErrorString(e));
+        if (hip_device >= n)
+            return create_failed(c, KNP_E_HIP, "device " + std::to_string(hip_device) + " of " +
+                                                   std::to_string(n) + " visible");
+        const hipError_t e2 = hipSetDevice(hip_device);
+        if (e2 != hipSuccess)
+            return create_failed(c, KNP_E_HIP, std::string("hipSetDevice: ") + hipGetErrorString(e2));
         try {
             c->d_flag.alloc(1);
         } catch (...) {
-            delete c;
-            return KNP_E_NOMEM;
+            return create_failed(c, KNP_E_NOMEM, "device allocation failed");
         }
     }
     *out = c;
@@ -244,7 +253,7 @@ void knp_destroy(knp_ctx *c) {
     delete c;
 }
 
-const char *knp_last_error(const knp_ctx *c) { return c ? c->err.c_str() : "NULL context"; }
+const char *knp_last_error(const knp_ctx *c) { return c ? c->err.c_str() : g_create_err.c_str(); }
 
 knp_status knp_mesh_upload(knp_ctx *c, int dim, int64_t n_vert, const double *xyz, int64_t n_elem,
                            const int32_t *elem_vert, const int32_t *elem_tag, int64_t pin_vertex,
@@ -304,6 +313,19 @@ knp_status knp_mesh_upload(knp_ctx *c, int dim, int64_t n_vert, const double *xy
             c->d_gidx.alloc(h.gidx.size());
             c->d_gidx.upload(h.gidx, s);
             c->d_gcoef.alloc(std::max<size_t>(1, ng) * GC_STRIDE);
+            c->d_thv.alloc(std::max<size_t>(1, ng));
+            {
+                std::vector<int64_t> row(h.n_cells + 1, 0);
+                for (size_t g = 0; g < ng; ++g) row[gcell[g]]++;   // gcell is 1-based
+                for (int32_t q = 0; q < h.n_cells; ++q) row[q + 1] += row[q];
+                std::vector<int32_t> col(std::max<size_t>(1, ng));
+                std::vector<int64_t> fill(row.begin(), row.end() - 1);
+                for (size_t g = 0; g < ng; ++g) col[fill[gcell[g] - 1]++] = int32_t(g);
+                c->d_cgrow.alloc(row.size());
+                c->d_cgrow.upload(row, s);
+                c->d_cgcol.alloc(col.size());
+                c->d_cgcol.upload(col, s);
+            }
             c->d_rowptr.alloc(h.rowptr.size());
             c->d_rowptr.upload(h.rowptr, s);
             c->d_colidx.alloc(h.colidx.size());
@@ -445,20 +467,28 @@ knp_status knp_assemble_step(knp_ctx *c, double t_n, double dt, const double *u_
         const auto ma = c->mesh_args();
         const auto ga = c->gamma_args();
         launch::membrane_coefficients(ga, p, h.Nr[0], h.Nr[1], u_prev, gates, theta, c->d_gcoef.p, s);
-        if (dt != c->dt_static) {
+        // values (scaled by the current S) and f; the membrane coefficients above
+        // are computed once per call, so running this twice advances no gate twice
+        auto matrix_and_rhs = [&](bool force_static) {
+            if (force_static || dt != c->dt_static) {
+                for (int r = 0; r < 2; ++r)
+                    launch::assemble_static(c->region(r), ma, p, c->d_rowptr.p, c->d_vals.p, c->d_sc.p, h.pin_dof, s);
+                c->dt_static = dt;
+            }
             for (int r = 0; r < 2; ++r)
-                launch::assemble_static(c->region(r), ma, p, c->d_rowptr.p, c->d_vals.p, c->d_sc.p, h.pin_dof, s);
-            c->dt_static = dt;
-        }
-        for (int r = 0; r < 2; ++r)
-            launch::assemble_dynamic(c->region(r), ma, p, c->d_rowptr.p, c->d_vals.p, c->d_sc.p, u_prev, f_out,
-                                     h.pin_dof, s);
-        launch::assemble_membrane(ga, ma, p, h.Nr[0], h.Nr[1], c->d_prow[0].p, c->d_prow[1].p, c->d_rowptr.p,
-                                  c->d_colidx.p, c->d_vals.p, c->d_sc.p, c->d_gcoef.p, f_out, s);
+                launch::assemble_dynamic(c->region(r), ma, p, c->d_rowptr.p, c->d_vals.p, c->d_sc.p, u_prev, f_out,
+                                         h.pin_dof, s);
+            launch::assemble_membrane(ga, ma, p, h.Nr[0], h.Nr[1], c->d_prow[0].p, c->d_prow[1].p, c->d_rowptr.p,
+                                      c->d_colidx.p, c->d_vals.p, c->d_sc.p, c->d_gcoef.p, f_out, s);
+        };
+        matrix_and_rhs(false);
         c->tm.end(KNP_TIMER_ASSEMBLY, t0, c->assembly_bytes, s);
         if (first) {
+            // S from the unscaled diagonal, then the same kernels again with S, so
+            // that this step's values round exactly as a later call on the same
+            // inputs (recomputed steps reproduce stored ones bit for bit)
             launch::scaling_from_diag(h.N, c->d_vals.p, c->d_diag.p, c->d_sc.p, s);
-            launch::rescale_system(h.N, c->d_rowptr.p, c->d_colidx.p, c->d_vals.p, c->d_sc.p, s);
+            matrix_and_rhs(true);
             // P_0: the diagonal blocks of the first (scaled) matrix, kept on the host for AMG setup
             std::vector<double> vals(h.nnz), sc(h.N);
             c->d_vals.download(vals.data(), h.nnz, s);
@@ -482,6 +512,9 @@ knp_status knp_assemble_step(knp_ctx *c, double t_n, double dt, const double *u_
         hip_check(hipGetLastError(), "assembly launch");
         hip_check(hipStreamSynchronize(s), "assembly");
         c->tm.harvest();
+        c->last_theta = theta;
+        c->last_t = t_n;
+        c->last_dt = dt;
         c->assembled = true;
         c->T_current = false;
         return KNP_OK;
@@ -626,12 +659,23 @@ knp_status knp_timing_read(knp_ctx *c, knp_timer *out) {
 knp_status knp_step_vjp(knp_ctx *c, const double *u_prev, const double *u_n, const double *lambda_n,
                         double *u_prev_bar, double *theta_bar) {
     return guarded(c, [&]() -> knp_status {
-        (void)u_prev;
-        (void)u_n;
-        (void)lambda_n;
-        (void)u_prev_bar;
-        (void)theta_bar;
-        return fail(c, KNP_E_STATE, "knp_step_vjp: not available in this build");
+        need_device(c);
+        if (!c->assembled) return fail(c, KNP_E_STATE, "knp_assemble_step of this step must come first");
+        if (!u_prev || !u_n || !lambda_n || !u_prev_bar) return fail(c, KNP_E_ARG, "NULL vector");
+        if (c->any_hh) return fail(c, KNP_E_ARG, "vector-Jacobian products support passive-leak membranes only");
+        hip_check(hipSetDevice(c->device), "set device");
+        const HostMesh &h = c->hm;
+        hipStream_t s = c->stream;
+        const auto p = c->phys(c->last_t, c->last_dt);
+        const auto ma = c->mesh_args();
+        for (int r = 0; r < 2; ++r)
+            launch::vjp_bulk(c->region(r), ma, p, u_n, lambda_n, u_prev_bar, h.pin_dof, s);
+        launch::vjp_membrane(c->gamma_args(), ma, p, h.Nr[0], h.Nr[1], c->d_prow[0].p, c->d_prow[1].p, u_prev, u_n,
+                             lambda_n, c->last_theta, u_prev_bar, c->d_thv.p, s);
+        if (theta_bar) launch::reduce_theta(h.n_cells, c->d_cgrow.p, c->d_cgcol.p, c->d_thv.p, theta_bar, s);
+        hip_check(hipGetLastError(), "vjp launch");
+        hip_check(hipStreamSynchronize(s), "vjp");
+        return KNP_OK;
     });
 }
 

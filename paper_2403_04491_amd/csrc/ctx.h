@@ -30,6 +30,11 @@ struct knp_ctx {
     knp::DArray<uint32_t> d_fpos[2];
     knp::DArray<int32_t> d_cell_model, d_cell_stim;
     knp::DArray<double> d_gcoef;
+    knp::DArray<int64_t> d_cgrow;   // membrane vertices of each cell (CSR)
+    knp::DArray<int32_t> d_cgcol;
+    knp::DArray<double> d_thv;      // per membrane vertex theta adjoint (VJP scratch)
+    const double *last_theta = nullptr;
+    double last_t = 0.0, last_dt = 0.0;
 
     // system
     knp::DArray<int64_t> d_rowptr, d_diag;

@@ -251,8 +251,6 @@ void assemble_dynamic(const RegionArgs &ra, const MeshArgs &ma, const PhysArgs &
 void assemble_membrane(const GammaArgs &g, const MeshArgs &ma, const PhysArgs &p, int64_t Ni, int64_t Ne,
                        const int64_t *prow_i, const int64_t *prow_e, const int64_t *rowptr, const int32_t *colidx,
                        double *vals, const double *sc, const double *gcoef, double *f, hipStream_t s);
-void rescale_system(int64_t N, const int64_t *rowptr, const int32_t *col, double *vals, const double *sc,
-                    hipStream_t s);
 void scaling_from_diag(int64_t N, const double *vals, const int64_t *diag_pos, double *sc, hipStream_t s);
 void gather(int64_t n, const double *src, const int64_t *map, double *dst, hipStream_t s);
 void scale_vec(int64_t n, const double *x, const double *sc, double *y, int invert, hipStream_t s);
@@ -291,12 +289,12 @@ void sub(int64_t n, const double *a, const double *b, double *y, hipStream_t s);
 int reduce_blocks(int64_t n);
 
 // adjoint
-void vjp_bulk(const RegionArgs &ra, const MeshArgs &ma, const PhysArgs &p, const int64_t *rowptr,
-              const double *u_prev, const double *u_n, const double *lam, double *u_prev_bar, hipStream_t s);
+void vjp_bulk(const RegionArgs &ra, const MeshArgs &ma, const PhysArgs &p, const double *u_n, const double *lam,
+              double *u_prev_bar, int64_t pin_dof, hipStream_t s);
 void vjp_membrane(const GammaArgs &g, const MeshArgs &ma, const PhysArgs &p, int64_t Ni, int64_t Ne,
-                  const double *u_prev, const double *u_n, const double *lam, const double *theta,
-                  double *u_prev_bar, double *theta_bar_vertex, hipStream_t s);
-void reduce_theta(int64_t n_gamma, const int32_t *gcell, const double *per_vertex, int n_cells,
+                  const int64_t *prow_i, const int64_t *prow_e, const double *u_prev, const double *u_n,
+                  const double *lam, const double *theta, double *u_prev_bar, double *theta_vertex, hipStream_t s);
+void reduce_theta(int n_cells, const int64_t *cg_row, const int32_t *cg_col, const double *theta_vertex,
                   double *theta_bar, hipStream_t s);
 
 }  // namespace launch

@@ -84,6 +84,14 @@ knp_status krylov_solve(knp_ctx *c, bool transpose, const double *b, double *x, 
     int its = 0, restarts = 0;
     double est = 1.0;
     bool converged = false;
+    // Attainable-accuracy floor: a cycle that ends on a converged recurrence
+    // estimate while the recomputed residual stays above rtol has met the rounding
+    // floor of ||S b - S A S y||.  After STALL_WINDOW such restarts in a row over
+    // which the recomputed residual has not halved, the solve stops (KNP_E_NOCONV).
+    constexpr int STALL_WINDOW = 50;
+    int stall = 0;
+    bool cycle_est_converged = false;
+    double window_beta = 0.0;
     while (true) {
         apply_operator(c, transpose, yh, w);
         launch::sub(N, bh, w, w, s);
@@ -95,6 +103,12 @@ knp_status krylov_solve(knp_ctx *c, bool transpose, const double *b, double *x, 
             break;
         }
         if (its >= o.max_it) break;
+        if (restarts > 0 && cycle_est_converged && beta > 0.5 * window_beta) {
+            if (++stall >= STALL_WINDOW) break;
+        } else {
+            stall = 0;
+            window_beta = beta;
+        }
         ++restarts;
         double *V = c->V.p;
         launch::axpby(N, 1.0 / beta, w, 0.0, V, s);
@@ -159,6 +173,7 @@ knp_status krylov_solve(knp_ctx *c, bool transpose, const double *b, double *x, 
             est = std::fabs(g[j + 1]) / bnorm;
             if (est <= o.rtol || its >= o.max_it || hn == 0.0) break;
         }
+        cycle_est_converged = est <= o.rtol;
         // y = H^{-1} g (upper triangular), x += Z y
         for (int i = jend - 1; i >= 0; --i) {
             double t = g[i];

@@ -69,6 +69,11 @@ def load_library(path: str = _LIB_PATH) -> C.CDLL:
     if not os.path.exists(path):
         raise ImportError(f"libknp.so not found at {path}; run paper_2403_04491_amd/build.py "
                           "(or __graft_entry__.build()) first")
+    # One HIP runtime per process: torch carries its own libamdhip64, and the
+    # library's dependency must resolve to that already-loaded runtime.  Loaded
+    # before torch, the library would bring in a second runtime whose device
+    # state torch's allocations and streams do not belong to.
+    import torch  # noqa: F401
     lib = C.CDLL(path)
     P, I64, I32, D = C.c_void_p, C.c_int64, C.c_int32, C.c_double
     lib.knp_create.argtypes = [C.POINTER(P), C.c_int, P]
@@ -153,7 +158,7 @@ class Context:
 
     def _check(self, st):
         if st != 0:
-            msg = self._lib.knp_last_error(self._c).decode() if self._c else ""
+            msg = self._lib.knp_last_error(self._c if self._c else None).decode()
             raise KnpError(st, msg)
 
     def close(self):

@@ -95,3 +95,23 @@ def test_host_only_context_rejects_device_calls():
     with pytest.raises(knp.KnpError) as ei:
         ctx.set_params(case.params, case.cell_model, case.cell_stim)
     assert ei.value.status == 2
+
+
+def test_one_hip_runtime_in_process():
+    """The binding loads libknp after torch, so both use torch's HIP runtime."""
+    import paper_2403_04491_amd  # noqa: F401
+    maps = open("/proc/self/maps").read().splitlines()
+    hip = {line.split()[-1] for line in maps if "libamdhip64" in line}
+    assert len(hip) == 1, hip
+
+
+def test_failed_create_reports_reason():
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("needs a host without a visible GPU")
+    lib = knp.lib()
+    c = ctypes.c_void_p()
+    st = lib.knp_create(ctypes.byref(c), 0, None)
+    assert knp.STATUS[st] == "KNP_E_HIP" and not c.value
+    msg = lib.knp_last_error(None).decode()
+    assert "hipGetDeviceCount" in msg or "visible" in msg, msg

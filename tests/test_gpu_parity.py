@@ -102,6 +102,23 @@ def test_assembly_matches_oracle(name):
             assert np.allclose(s.gates.cpu().numpy()[hh], w_ref[hh], rtol=1e-13, atol=1e-15)
 
 
+
+def test_first_assembly_repeats_bit_for_bit():
+    """The first call (which also fixes S) and a later call on the same inputs give
+    identical values and f, so recomputed steps reproduce stored ones exactly."""
+    case = model_a_case(3, 8, "hh", 5e-5, 2, cfg_id=2)
+    s = KnpSolver(case)
+    g0 = s.gates.clone()
+    out = []
+    for _ in range(2):
+        s.gates = g0.clone()
+        s.assemble(1)
+        vals = torch.empty(s.info.nnz_A, dtype=torch.float64, device=DEV)
+        s.ctx.get_values(vals)
+        out.append((vals.cpu().numpy(), s.f.cpu().numpy(), s.gates.cpu().numpy()))
+    for a, b in zip(*out):
+        assert np.array_equal(a, b)
+
 # ---------------------------------------------------------------------------- operators
 @pytest.fixture(scope="module")
 def solver3d():
@@ -221,12 +238,14 @@ def test_time_steps_match_oracle(name, steps, precision, tol):
 
 def test_paper_tolerance_iterations_and_error():
     """At the paper's rtol 1e-6 and GMRES(30), smooth steps take a handful of
-    iterations; the error against the oracle is reported, not bounded at 1e-8."""
+    iterations; the error against the oracle is reported, not bounded at 1e-8.
+    The first step starts from the seeded noise of u_0, whose near-null modes
+    stall GMRES(30) near 3e-6; it runs with restart 200, as in the benchmark."""
     case = config_case(1)
     s = KnpSolver(case, solve=solve_opts(rtol=1e-6, restart=30, max_it=2000))
     ref = timeloop.run(case, n_steps=5)["u"]
-    its = []
-    for n in range(1, 6):
+    its = [s.step(opts=solve_opts(rtol=1e-6, restart=200, max_it=2000)).its]
+    for n in range(2, 6):
         its.append(s.step().its)
     print(f"  GMRES(30) iterations per step at rtol 1e-6: {its}", flush=True)
     assert max(its[2:]) <= 20, its
