@@ -282,17 +282,22 @@ void DevCsr::upload(const Csr &h, bool fp32, hipStream_t s) {
         blk.alloc(b.size());
         blk.upload(b, s);
     }
-    col.alloc(std::max<size_t>(1, h.col.size()));
-    if (!h.col.empty()) col.upload(h.col, s);
+    std::vector<int32_t> c(h.col);
+    c.resize(h.col.size() + STREAM_PAD, 0);
+    col.alloc(c.size());
+    col.upload(c, s);
     if (fp32) {
         std::vector<float> v(h.val.begin(), h.val.end());
-        val32.alloc(std::max<size_t>(1, v.size()));
-        if (!v.empty()) val32.upload(v, s);
-        hip_check(hipStreamSynchronize(s), "upload");
+        v.resize(h.val.size() + STREAM_PAD, 0.0f);
+        val32.alloc(v.size());
+        val32.upload(v, s);
     } else {
-        val64.alloc(std::max<size_t>(1, h.val.size()));
-        if (!h.val.empty()) val64.upload(h.val, s);
+        std::vector<double> v(h.val);
+        v.resize(h.val.size() + STREAM_PAD, 0.0);
+        val64.alloc(v.size());
+        val64.upload(v, s);
     }
+    hip_check(hipStreamSynchronize(s), "upload");
 }
 
 Amg::~Amg() { clear(); }

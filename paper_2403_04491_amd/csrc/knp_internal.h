@@ -134,6 +134,10 @@ struct CsrView {
 };
 
 constexpr int STREAM_CAP = 2048;   // entries per row block (8 per thread of 256)
+// Zeroed entries after the column indices and values of every level matrix: the
+// FP32 stream reads 4 consecutive entries per lane from a 4-aligned start, up to
+// 3 entries past a block's end.
+constexpr int STREAM_PAD = 4;
 // Row-block boundaries for the block-streamed kernels; throws if a row is longer
 // than STREAM_CAP.
 std::vector<int32_t> row_blocks(const int64_t *rowptr, int64_t nrows);

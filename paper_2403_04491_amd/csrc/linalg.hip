@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "knp_internal.h"
 
@@ -35,10 +36,8 @@ __device__ inline A group_sum(A v) {
     return v;
 }
 
-template <typename T>
-__device__ inline T ldg_stream(const T *p) {
-    return __builtin_nontemporal_load(p);
-}
+typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // ---------------------------------------------------------------- block-streamed CSR
 // Block b owns rows blk[b]..blk[b+1]-1, whose entries (at most STREAM_CAP) are
@@ -48,11 +47,16 @@ __device__ inline T ldg_stream(const T *p) {
 // the products in LDS.  Phase 2: each row is summed from LDS in a fixed order
 // by one thread and handed to the epilogue (plain store, residual, Chebyshev
 // update, prolongation add).  Deterministic: no atomics, fixed summation order.
+//
+// FP32 matrices (the AMG levels) stream 16 bytes of indices and 16 bytes of
+// values per lane: each lane takes 4 consecutive entries from the block's
+// start rounded down to a multiple of 4, skipping entries outside the block (the
+// arrays carry STREAM_PAD zeroed entries, so the rounded loads stay in bounds).
+// The products and their summation order are the same as the scalar stream's.
 template <typename TM, typename TX, typename A, class Epi>
 __device__ inline void stream_rows(const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col,
                                    const TM *__restrict__ val, const TX *__restrict__ x,
                                    const int32_t *__restrict__ blk, int nblk, Epi &epi) {
-    constexpr int PER = STREAM_CAP / TPB;
     __shared__ A prod[STREAM_CAP];
     // blocks in launch order (a per-XCD contiguous remapping measured slower)
     const int lb = int(blockIdx.x);
@@ -60,20 +64,49 @@ __device__ inline void stream_rows(const int64_t *__restrict__ rowptr, const int
     const int32_t r0 = blk[lb], r1 = blk[lb + 1];
     const int64_t k0 = rowptr[r0];
     const int n = int(rowptr[r1] - k0);
-    int32_t c[PER];
-    TM v[PER];
+    if constexpr (std::is_same<TM, float>::value) {
+        static_assert(STREAM_PAD >= 3, "the 4-wide stream reads up to 3 entries past a block");
+        constexpr int UNITS = STREAM_CAP / (4 * TPB) + 1;
+        const int64_t ka = k0 & ~int64_t(3);
+        const int lead = int(k0 - ka);
+        i32x4 c[UNITS];
+        f32x4 v[UNITS];
 #pragma unroll
-    for (int u = 0; u < PER; ++u) {
-        const int i = threadIdx.x + u * TPB;
-        if (i < n) {
-            c[u] = __builtin_nontemporal_load(col + k0 + i);
-            v[u] = __builtin_nontemporal_load(val + k0 + i);
+        for (int u = 0; u < UNITS; ++u) {
+            const int off = u * 4 * TPB + 4 * int(threadIdx.x);   // from ka
+            if (off < lead + n) {
+                c[u] = __builtin_nontemporal_load(reinterpret_cast<const i32x4 *>(col + ka + off));
+                v[u] = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(val + ka + off));
+            }
         }
-    }
 #pragma unroll
-    for (int u = 0; u < PER; ++u) {
-        const int i = threadIdx.x + u * TPB;
-        if (i < n) prod[i] = A(v[u]) * A(x[c[u]]);
+        for (int u = 0; u < UNITS; ++u) {
+            const int off = u * 4 * TPB + 4 * int(threadIdx.x);
+            if (off < lead + n) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int i = off + q - lead;
+                    if (i >= 0 && i < n) prod[i] = A(v[u][q]) * A(x[c[u][q]]);
+                }
+            }
+        }
+    } else {
+        constexpr int PER = STREAM_CAP / TPB;
+        int32_t c[PER];
+        TM v[PER];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int i = threadIdx.x + u * TPB;
+            if (i < n) {
+                c[u] = __builtin_nontemporal_load(col + k0 + i);
+                v[u] = __builtin_nontemporal_load(val + k0 + i);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int i = threadIdx.x + u * TPB;
+            if (i < n) prod[i] = A(v[u]) * A(x[c[u]]);
+        }
     }
     __syncthreads();
     for (int32_t row = r0 + int32_t(threadIdx.x); row < r1; row += TPB) {
