@@ -161,6 +161,180 @@ def kernels_only(solver, args, amg_kw, log):
     print(json.dumps(out), flush=True)
 
 
+def adjoint_bench(args, log):
+    """Gradient of the probe objective on the 2x2x2 lattice (~2e6 unknowns): one
+    checkpointed forward + reverse sweep over the full horizon, timed at the given
+    tolerances; then, on a short horizon (the first --fd-steps steps), the
+    gradient at tight tolerances against central differences on 4 cells."""
+    import numpy as np
+    import torch
+    from knp_inputs import config_case
+    from paper_2403_04491_amd.adjoint import AdjointProblem
+
+    case = config_case(4, per_pitch=args.adj_per_pitch, n_steps=args.adj_steps)
+    dev = torch.device("cuda", 0)
+    theta = torch.tensor(case.theta, dtype=torch.float64, device=dev)
+    log(f"case {case.name}: {case.n_vert} vertices, {case.n_elem} tets, {args.adj_steps} steps")
+
+    def progress(msg):
+        print(f"  {msg}", file=sys.stderr, flush=True)
+
+    def timed_gradient(rtol, adj_rtol):
+        prob = AdjointProblem(case, every=args.adj_every, rtol=rtol, adj_rtol=adj_rtol, restart=args.adj_restart,
+                              progress=progress, max_it=8000)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        J, ckpt = prob.forward(theta)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        g = prob.gradient(theta, ckpt)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        n = case.n_steps
+        fwd_its = prob.stats["forward_its"]
+        return prob, float(J), g.cpu().numpy(), {
+            "forward_s": round(t1 - t0, 3), "reverse_s": round(t2 - t1, 3),
+            "forward_its_per_step": round(sum(fwd_its[:n]) / n, 2),
+            "forward_rel_res_max": max(prob.stats["forward_rel_res"][:n]),
+            "adjoint_its_per_step": round(sum(prob.stats["adjoint_its"]) / n, 2),
+            "adjoint_rel_res_max": max(prob.stats["adjoint_rel_res"]),
+            "checkpoints": len(ckpt), "checkpoint_bytes": int(sum(v.numel() * 8 for v in ckpt.values()))}
+
+    log(f"[timed gradient] {case.n_steps} steps, forward rtol {args.adj_rtol_fwd}, adjoint rtol {args.adj_rtol_adj}")
+    _, J_fast, g_fast, t_fast = timed_gradient(args.adj_rtol_fwd, args.adj_rtol_adj)
+    log(f"  {t_fast}")
+    n_full = case.n_steps
+    case.n_steps = args.fd_steps
+    log(f"[check gradient] {case.n_steps} steps, forward rtol {args.fd_rtol_fwd}, adjoint rtol {args.fd_rtol_adj}")
+    prob, J, g, t_tight = timed_gradient(args.fd_rtol_fwd, args.fd_rtol_adj)
+    log(f"  {t_tight}")
+    log(f"[check gradient, timed-run adjoint rtol {args.adj_rtol_adj}]")
+    _, _, g_loose, _ = timed_gradient(args.fd_rtol_fwd, args.adj_rtol_adj)
+    rng = np.random.default_rng(4004)
+    cells = sorted(int(c) for c in rng.choice(len(case.theta), size=min(args.fd_cells, len(case.theta)), replace=False))
+    gmax = float(np.abs(g).max())
+    fd = []
+    for h in (1e-6, 1e-3):
+        for c in cells:
+            tp = case.theta.copy()
+            tm = case.theta.copy()
+            tp[c] *= 1.0 + h
+            tm[c] *= 1.0 - h
+            Jp, _ = prob.forward(torch.tensor(tp, dtype=torch.float64, device=dev))
+            Jm, _ = prob.forward(torch.tensor(tm, dtype=torch.float64, device=dev))
+            d = (float(Jp) - float(Jm)) / (2.0 * h * case.theta[c])
+            fd.append({"h_rel": h, "cell": c, "fd": d, "adjoint": float(g[c]),
+                       "rel_err_vs_max": abs(d - g[c]) / gmax, "rel_err": abs(d - g[c]) / abs(g[c])})
+            log(f"  FD h={h:g} cell {c}: fd {d:.6e} adjoint {g[c]:.6e} rel err {abs(d - g[c]) / abs(g[c]):.2e}")
+    steps_per_s = n_full / (t_fast["forward_s"] + t_fast["reverse_s"])
+    out = {
+        "metric": "adjoint gradient of a time-integrated extracellular-potential objective w.r.t. per-cell leak "
+                  "conductances at ~2e6 unknowns (forward + checkpointed reverse sweep)",
+        "value": round(steps_per_s, 3),
+        "unit": "time steps/s (forward + adjoint)",
+        "n_gpus": 1, "higher_is_better": True, "dtype": "f64", "data": "synthetic", "vs_baseline": None,
+        "config": {"workload": f"2x2x2 lattice of jittered box cells, {case.shape[0]}^3 grid x 6 tets, "
+                               f"N={prob.solver.info.N} unknowns, 8 passive-leak cells with log-uniform leak factors, "
+                               f"16 probes, dt=0.05 ms, {n_full} steps, checkpoints every {args.adj_every}",
+                   "N": prob.solver.info.N, "n_cells": len(case.theta)},
+        "timed": {"steps": n_full, "forward_rtol": args.adj_rtol_fwd, "adjoint_rtol": args.adj_rtol_adj,
+                  **t_fast, "J": J_fast, "gradient": [float(v) for v in g_fast]},
+        "check": {"steps": case.n_steps, "forward_rtol": args.fd_rtol_fwd, "adjoint_rtol": args.fd_rtol_adj,
+                  **t_tight, "J": J, "gradient": [float(v) for v in g],
+                  "gradient_rel_diff_at_timed_adjoint_rtol": float(np.abs(g_loose - g).max() / gmax),
+                  "central_differences": fd},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def large_bench(args, log):
+    """The 8x8x8 lattice of elongated cells (~1.1e8 unknowns), FP32-stored AMG:
+    device memory after each phase, the first step at rtol 1e-6 against the same
+    system solved to rtol 1e-9 in FP64 FGMRES, then timed steps."""
+    import numpy as np
+    import torch
+    from knp_inputs import config_case
+    from paper_2403_04491_amd import KnpSolver, amg_opts, solve_opts
+
+    mem = {}
+    total = torch.cuda.mem_get_info(0)[1]
+
+    def sample(tag):
+        free = torch.cuda.mem_get_info(0)[0]
+        mem[tag] = round((total - free) / 2**30, 2)
+        log(f"  device memory in use after {tag}: {mem[tag]} GiB")
+
+    t0 = time.perf_counter()
+    case = config_case(5, per_pitch=args.large_per_pitch, n_steps=1 + args.large_steps)
+    log(f"case {case.name}: {case.n_vert} vertices, {case.n_elem} tets, generated in {time.perf_counter() - t0:.1f} s")
+    sample("start")
+    t0 = time.perf_counter()
+    solver = KnpSolver(case, amg=amg_opts(precision=1), solve=solve_opts(rtol=1e-6, restart=30, max_it=2000))
+    torch.cuda.synchronize()
+    t_upload = time.perf_counter() - t0
+    info = solver.info
+    log(f"mesh upload {t_upload:.1f} s: N={info.N} nnz(A)={info.nnz_A} nnz(P0)={info.nnz_P0}")
+    sample("mesh upload")
+    t0 = time.perf_counter()
+    solver.assemble(1)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    stats = solver.ctx.amg_stats()
+    log(f"first assembly + AMG setup {t_setup:.1f} s: levels rows {stats['rows']} nnz {stats['nnz']}")
+    sample("AMG setup")
+    u0 = solver.u.clone()
+    t0 = time.perf_counter()
+    x, inf1, ok1 = solver.solve(allow_noconv=True,
+                                opts=solve_opts(rtol=1e-6, restart=args.large_first_restart, max_it=3000))
+    torch.cuda.synchronize()
+    t_first = time.perf_counter() - t0
+    log(f"step 1 at rtol 1e-6: {inf1.its} its, rel_res {inf1.rel_res:.2e}, {t_first:.1f} s")
+    sample("step 1 (FP32 AMG, rtol 1e-6)")
+    solver.u = x                    # the reference continues from the rtol-1e-6 iterate
+    t0 = time.perf_counter()
+    ref, inf_ref, ok_ref = solver.solve(allow_noconv=True,
+                                        opts=solve_opts(rtol=1e-9, restart=args.large_first_restart, max_it=6000))
+    torch.cuda.synchronize()
+    log(f"step 1 reference at rtol 1e-9: {inf_ref.its} its, rel_res {inf_ref.rel_res:.2e}, "
+        f"{time.perf_counter() - t0:.1f} s")
+    err = block_errors(info, x.cpu().numpy(), ref.cpu().numpy())
+    log(f"  step-1 error of the rtol-1e-6 FP32-AMG solve vs the rtol-1e-9 solve: {err}")
+    del ref
+    solver.u = x
+    solver.n = 1
+    its, times = [], []
+    for k in range(args.large_steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        inf = solver.step()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        its.append(inf.its)
+        log(f"  step {solver.n}: {inf.its} its, rel_res {inf.rel_res:.2e}, {times[-1] * 1e3:.0f} ms")
+    sample("timed steps")
+    timed = times[1:] if len(times) > 1 else times
+    ms = 1e3 * float(np.median(timed))
+    out = {
+        "metric": "time steps/s at ~1e8 unknowns (FP32-AMG FGMRES), peak device memory, step-1 error vs FP64",
+        "value": round(1e3 / ms, 3), "unit": "time steps/s", "n_gpus": 1, "steps": len(timed),
+        "ms_per_step": round(ms, 1), "higher_is_better": True, "dtype": "f64 (AMG levels f32)",
+        "data": "synthetic", "vs_baseline": None,
+        "config": {"workload": f"8x8x8 lattice of 4:1:1 jittered box cells, {case.shape[0]}x{case.shape[1]}x"
+                               f"{case.shape[2]} grid x 6 tets, N={info.N} unknowns, passive leak, dt=0.05 ms, "
+                               f"FGMRES(30) rtol 1e-6",
+                   "N": info.N, "nnz_A": info.nnz_A, "nnz_P0": info.nnz_P0},
+        "its_per_step": its, "step_ms": [round(t * 1e3, 1) for t in times],
+        "first_step": {"restart": args.large_first_restart, "its": inf1.its, "rel_res": inf1.rel_res,
+                       "converged": ok1, "s": round(t_first, 2),
+                       "reference_its": inf_ref.its, "reference_rel_res": inf_ref.rel_res,
+                       "reference_converged": ok_ref, "rel_err_vs_reference": err},
+        "setup_s": {"mesh_upload": round(t_upload, 1), "first_assembly_and_amg_setup": round(t_setup, 1)},
+        "amg_hierarchy": stats,
+        "device_memory_gib": mem, "device_memory_total_gib": round(total / 2**30, 1),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -183,6 +357,23 @@ def main():
                          "1 GiB device copy that calibrates the HBM byte counters")
     ap.add_argument("--reps", type=int, default=10)
     ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--adjoint", action="store_true",
+                    help="gradient benchmark on the 2x2x2 lattice instead of the step throughput")
+    ap.add_argument("--adj-per-pitch", type=int, default=39, help="39 = ~2e6 unknowns")
+    ap.add_argument("--adj-steps", type=int, default=40)
+    ap.add_argument("--adj-every", type=int, default=8)
+    ap.add_argument("--adj-restart", type=int, default=200)
+    ap.add_argument("--adj-rtol-fwd", type=float, default=1e-8)
+    ap.add_argument("--adj-rtol-adj", type=float, default=1e-6)
+    ap.add_argument("--fd-cells", type=int, default=4)
+    ap.add_argument("--large", action="store_true",
+                    help="the ~1e8-unknown lattice of elongated cells with FP32-stored AMG")
+    ap.add_argument("--large-per-pitch", type=int, default=None, help="default 23 (~1.1e8 unknowns)")
+    ap.add_argument("--large-steps", type=int, default=9)
+    ap.add_argument("--large-first-restart", type=int, default=60)
+    ap.add_argument("--fd-steps", type=int, default=4, help="horizon of the finite-difference check")
+    ap.add_argument("--fd-rtol-fwd", type=float, default=1e-11)
+    ap.add_argument("--fd-rtol-adj", type=float, default=1e-8)
     args = ap.parse_args()
 
     def log(msg):
@@ -195,6 +386,12 @@ def main():
         print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1 "
                                    "(the multi-GPU sharding is a design, not a code path)"}))
         sys.exit(2)
+    if args.adjoint:
+        adjoint_bench(args, log)
+        return
+    if args.large:
+        large_bench(args, log)
+        return
     import torch
     from knp_inputs import config_case
     from paper_2403_04491_amd import KnpSolver, solve_opts

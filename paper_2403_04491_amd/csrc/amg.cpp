@@ -255,14 +255,14 @@ void invert_dense(int n, std::vector<double> &a) {   // Gauss-Jordan, partial pi
 
 }  // namespace
 
-std::vector<int32_t> row_blocks(const int64_t *rowptr, int64_t nrows) {
+std::vector<int32_t> row_blocks(const int64_t *rowptr, int64_t nrows, int64_t cap) {
     std::vector<int32_t> b;
     b.push_back(0);
     int64_t r = 0;
     while (r < nrows) {
         const int64_t k0 = rowptr[r];
         int64_t e = r;
-        while (e < nrows && rowptr[e + 1] - k0 <= STREAM_CAP && e - r < STREAM_CAP) ++e;
+        while (e < nrows && rowptr[e + 1] - k0 <= cap && e - r < cap) ++e;
         if (e == r) throw Error{KNP_E_ARG, "a matrix row is longer than the streaming block capacity"};
         b.push_back(int32_t(e));
         r = e;
@@ -309,6 +309,84 @@ void Amg::clear() {
     level_nnz.clear();
     level_n.clear();
 }
+
+namespace {
+
+// P_0 in the field-block layout: the entries of region r's scalar pattern once,
+// each with its four field values.  p0_vals holds P_0 block by block: for region
+// r and field f the region's scalar pattern in row order.
+void upload_field_blocks(DevFieldBlock &fb, const HostMesh &m, const std::vector<double> &p0_vals, bool fp32,
+                         hipStream_t s) {
+    const int64_t nnz0 = m.prow[0][m.Nr[0]], nnz1 = m.prow[1][m.Nr[1]];
+    fb.Ni = m.Nr[0];
+    fb.Ne = m.Nr[1];
+    fb.nv = fb.Ni + fb.Ne;
+    fb.nnz = nnz0 + nnz1;
+    std::vector<int64_t> rp(fb.nv + 1);
+    for (int64_t j = 0; j <= fb.Ni; ++j) rp[j] = m.prow[0][j];
+    for (int64_t j = 1; j <= fb.Ne; ++j) rp[fb.Ni + j] = nnz0 + m.prow[1][j];
+    std::vector<int32_t> col(std::max<int64_t>(1, fb.nnz));
+    std::copy(m.pcol[0].begin(), m.pcol[0].begin() + nnz0, col.begin());
+    std::copy(m.pcol[1].begin(), m.pcol[1].begin() + nnz1, col.begin() + nnz0);
+    // row blocks per region, region e's rows after region i's
+    std::vector<int32_t> blk = row_blocks(m.prow[0].data(), fb.Ni, FB_CAP);
+    {
+        std::vector<int32_t> be = row_blocks(m.prow[1].data(), fb.Ne, FB_CAP);
+        for (size_t q = 1; q < be.size(); ++q) blk.push_back(int32_t(fb.Ni + be[q]));
+    }
+    fb.nblk = int64_t(blk.size()) - 1;
+    std::vector<double> v(std::max<int64_t>(4, 4 * fb.nnz));
+    const int64_t pbase[2] = {0, 4 * nnz0}, nnzr[2] = {nnz0, nnz1}, kbase[2] = {0, nnz0};
+    for (int r = 0; r < 2; ++r)
+#pragma omp parallel for schedule(static)
+        for (int64_t k = 0; k < nnzr[r]; ++k)
+            for (int f = 0; f < 4; ++f) v[4 * (kbase[r] + k) + f] = p0_vals[pbase[r] + f * nnzr[r] + k];
+    fb.rowptr.alloc(rp.size());
+    fb.rowptr.upload(rp, s);
+    fb.col.alloc(col.size());
+    fb.col.upload(col, s);
+    fb.blk.alloc(blk.size());
+    fb.blk.upload(blk, s);
+    if (fp32) {
+        std::vector<float> v32(v.begin(), v.end());
+        fb.val32.alloc(v32.size());
+        fb.val32.upload(v32, s);
+    } else {
+        fb.val64.alloc(v.size());
+        fb.val64.upload(v, s);
+    }
+    hip_check(hipStreamSynchronize(s), "field-block upload");
+}
+
+// Level 0's vectors are interleaved by field, so the prolongation's rows and the
+// restriction's columns move from off_r + f N_r + j to off_r + 4 j + f.
+void interleave_level0_transfer(Csr &P, Csr &R, const HostMesh &m) {
+    const int64_t N = m.N;
+    std::vector<int32_t> to4(N);
+    for (int r = 0; r < 2; ++r)
+        for (int f = 0; f < 4; ++f)
+            for (int64_t j = 0; j < m.Nr[r]; ++j) to4[m.off[r] + f * m.Nr[r] + j] = int32_t(m.off[r] + 4 * j + f);
+    for (auto &c : R.col) c = to4[c];
+    Csr Q;
+    Q.nrows = P.nrows;
+    Q.ncols = P.ncols;
+    Q.rowptr.assign(N + 1, 0);
+    for (int64_t i = 0; i < N; ++i) Q.rowptr[to4[i] + 1] = P.rowptr[i + 1] - P.rowptr[i];
+    for (int64_t i = 0; i < N; ++i) Q.rowptr[i + 1] += Q.rowptr[i];
+    Q.col.resize(P.col.size());
+    Q.val.resize(P.val.size());
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < N; ++i) {
+        int64_t o = Q.rowptr[to4[i]];
+        for (int64_t k = P.rowptr[i]; k < P.rowptr[i + 1]; ++k, ++o) {
+            Q.col[o] = P.col[k];
+            Q.val[o] = P.val[k];
+        }
+    }
+    P = std::move(Q);
+}
+
+}  // namespace
 
 void amg_build(Amg &amg, const HostMesh &m, const std::vector<double> &p0_vals, const std::vector<double> &near_null,
                const knp_amg_opts &o, hipStream_t s) {
@@ -530,7 +608,12 @@ void amg_build(Amg &amg, const HostMesh &m, const std::vector<double> &p0_vals, 
         amg.level_nnz.push_back(H[l].A.nnz());
         const bool last = l + 1 == H.size();
         if (!last) {
-            L->A.upload(H[l].A, f32, s);
+            if (l == 0) {
+                upload_field_blocks(L->fb, m, p0_vals, f32, s);
+                interleave_level0_transfer(H[0].P, H[0].R, m);
+            } else {
+                L->A.upload(H[l].A, f32, s);
+            }
             L->P.upload(H[l].P, f32, s);
             L->R.upload(H[l].R, f32, s);
         }
@@ -596,6 +679,7 @@ struct LV<double> {
     static double *t(Level *L) { return L->t64.p; }
     static double *d(Level *L) { return L->d64.p; }
     static const double *A(Level *L) { return L->A.val64.p; }
+    static const double *FB(Level *L) { return L->fb.val64.p; }
     static const double *P(Level *L) { return L->P.val64.p; }
     static const double *R(Level *L) { return L->R.val64.p; }
 };
@@ -607,6 +691,7 @@ struct LV<float> {
     static float *t(Level *L) { return L->t32.p; }
     static float *d(Level *L) { return L->d32.p; }
     static const float *A(Level *L) { return L->A.val32.p; }
+    static const float *FB(Level *L) { return L->fb.val32.p; }
     static const float *P(Level *L) { return L->P.val32.p; }
     static const float *R(Level *L) { return L->R.val32.p; }
 };
@@ -630,16 +715,25 @@ T *vcycle_level(Amg &amg, size_t l, const T *b, hipStream_t s, Timers *tm, T *ou
     }
     std::vector<std::pair<double, double>> cc;
     cheb_coeffs(L->lmax, amg.ratio, amg.degree, cc);
-    const int64_t n = L->n, nnz = L->A.nnz;
-    const T *av = LV<T>::A(L);
+    const int64_t n = L->n;
+    const bool fbl = l == 0;     // level 0 is P_0 in the field-block layout
+    const T *av = fbl ? LV<T>::FB(L) : LV<T>::A(L);
     T *x = LV<T>::x(L), *x2 = LV<T>::x2(L), *d = LV<T>::d(L), *t = LV<T>::t(L);
     // algorithmic bytes: values + column indices once, row pointers, each vector once
     const double vb = double(sizeof(T));
-    const double mat = double(nnz) * (vb + 4.0) + 8.0 * double(n + 1);
+    const double mat = fbl ? double(L->fb.nnz) * (4.0 * vb + 4.0) + 8.0 * double(L->fb.nv + 1)
+                           : double(L->A.nnz) * (vb + 4.0) + 8.0 * double(n + 1);
     Timers *t0 = (l == 0) ? tm : nullptr;
+    // on level 0 the final step (xout == out) writes the field-major output directly
     auto cheb = [&](const T *xin, T *xout, double c1, double c2) {
         hipEvent_t e = t0 ? t0->begin(KNP_TIMER_CHEB_L0, s) : nullptr;
-        launch::cheb_step<T>(L->A.view(), av, xin, b, d, xout, c1, c2, s);
+        if (fbl) {
+            const bool to_out = out && xout == out;
+            launch::fb_cheb_step<T>(L->fb.view(), av, xin, b, d, to_out ? nullptr : xout, to_out ? out : nullptr, c1,
+                                    c2, s);
+        } else {
+            launch::cheb_step<T>(L->A.view(), av, xin, b, d, xout, c1, c2, s);
+        }
         if (t0) {
             const double bytes = xin ? mat + vb * double(n) * (c1 != 0.0 ? 5.0 : 4.0) : 3.0 * vb * double(n);
             t0->end(KNP_TIMER_CHEB_L0, e, bytes, s);
@@ -654,7 +748,10 @@ T *vcycle_level(Amg &amg, size_t l, const T *b, hipStream_t s, Timers *tm, T *ou
     // residual and restriction
     {
         hipEvent_t e = t0 ? t0->begin(KNP_TIMER_RESID_L0, s) : nullptr;
-        launch::residual<T>(L->A.view(), av, x, b, t, s);
+        if (fbl)
+            launch::fb_residual<T>(L->fb.view(), av, x, b, t, s);
+        else
+            launch::residual<T>(L->A.view(), av, x, b, t, s);
         if (t0) t0->end(KNP_TIMER_RESID_L0, e, mat + 3.0 * vb * double(n), s);
     }
     Level *Lc = amg.levels[l + 1];
@@ -677,15 +774,26 @@ T *vcycle_level(Amg &amg, size_t l, const T *b, hipStream_t s, Timers *tm, T *ou
 void amg_vcycle(Amg &amg, const double *v, void *z, hipStream_t s, Timers *tm) {
     Level *L0 = amg.levels[0];
     const int64_t n = L0->n;
+    // with a coarser level, level 0 runs in the field-block layout: its right-hand
+    // side is v interleaved by field; the last smoothing step writes z field-major
+    const bool fbl = amg.levels.size() > 1;
     hipEvent_t e = tm ? tm->begin(KNP_TIMER_VCYCLE, s) : nullptr;
     if (amg.fp32) {
-        launch::convert<double, float>(n, v, L0->b32.p, s);
+        if (fbl)
+            launch::to_fields4<double, float>(L0->fb.Ni, L0->fb.Ne, v, L0->b32.p, s);
+        else
+            launch::convert<double, float>(n, v, L0->b32.p, s);
         float *zf = static_cast<float *>(z);
         float *x = vcycle_level<float>(amg, 0, L0->b32.p, s, tm, zf);
         if (x != zf) hip_check(hipMemcpyAsync(z, x, size_t(n) * sizeof(float), hipMemcpyDeviceToDevice, s), "copy");
     } else {
         double *zd = static_cast<double *>(z);
-        double *x = vcycle_level<double>(amg, 0, v, s, tm, zd);
+        const double *b = v;
+        if (fbl) {
+            launch::to_fields4<double, double>(L0->fb.Ni, L0->fb.Ne, v, L0->b64.p, s);
+            b = L0->b64.p;
+        }
+        double *x = vcycle_level<double>(amg, 0, b, s, tm, zd);
         if (x != zd) hip_check(hipMemcpyAsync(z, x, size_t(n) * sizeof(double), hipMemcpyDeviceToDevice, s), "copy");
     }
     if (tm) tm->end(KNP_TIMER_VCYCLE, e, 0.0, s);

@@ -140,7 +140,7 @@ constexpr int STREAM_CAP = 2048;   // entries per row block (8 per thread of 256
 constexpr int STREAM_PAD = 4;
 // Row-block boundaries for the block-streamed kernels; throws if a row is longer
 // than STREAM_CAP.
-std::vector<int32_t> row_blocks(const int64_t *rowptr, int64_t nrows);
+std::vector<int32_t> row_blocks(const int64_t *rowptr, int64_t nrows, int64_t cap = STREAM_CAP);
 
 struct DevCsr {
     int64_t nrows = 0, ncols = 0, nnz = 0;
@@ -163,10 +163,47 @@ struct DevCsr {
     }
 };
 
+// The finest AMG level is P_0, whose four field blocks in a region share that
+// region's scalar pattern (rows and columns by region vertex).  It is stored once
+// per vertex pair with the four field values side by side: block row v is region
+// vertex v (region i first, then region e), its entries index region-local
+// vertices, and vals[4k + f] is the field-f value of entry k.  Level-0 vectors are
+// interleaved by field: (region r, field f, local vertex j) sits at off_r + 4 j + f
+// (the solver's own order is off_r + f N_r + j); the restriction's columns and the
+// prolongation's rows on level 0 are numbered the same way.
+constexpr int FB_CAP = 1024;        // vertex-pair entries per row block (4 products each)
+struct FieldBlockView {
+    int64_t nv = 0, nnz = 0, nblk = 0;   // block rows, entries, row blocks
+    int64_t Ni = 0, Ne = 0;
+    const int64_t *rowptr = nullptr;     // [nv+1]
+    const int32_t *col = nullptr;        // [nnz + STREAM_PAD], region-local vertex
+    const int32_t *blk = nullptr;        // [nblk+1]; no block straddles the regions
+};
+struct DevFieldBlock {
+    int64_t nv = 0, nnz = 0, nblk = 0, Ni = 0, Ne = 0;
+    DArray<int64_t> rowptr;
+    DArray<int32_t> col, blk;
+    DArray<double> val64;                // [4 (nnz + STREAM_PAD)]
+    DArray<float> val32;
+    FieldBlockView view() const {
+        FieldBlockView v;
+        v.nv = nv;
+        v.nnz = nnz;
+        v.nblk = nblk;
+        v.Ni = Ni;
+        v.Ne = Ne;
+        v.rowptr = rowptr.p;
+        v.col = col.p;
+        v.blk = blk.p;
+        return v;
+    }
+};
+
 struct Level {
     int64_t n = 0;
     double lmax = 2.0;           // spectral radius estimate of the (unit-diagonal) operator
-    DevCsr A, P, R;              // P: n x n_coarse, R = P^T
+    DevCsr A, P, R;              // P: n x n_coarse, R = P^T (A unused on level 0)
+    DevFieldBlock fb;            // level 0 only: P_0 in the field-block layout
     // level vectors (precision of the hierarchy); x2 is the Chebyshev ping-pong buffer
     DArray<double> b64, x64, x2_64, t64, d64;
     DArray<float> b32, x32, x2_32, t32, d32;
@@ -272,6 +309,17 @@ void cheb_step(const CsrView &A, const T *val, const T *x_in, const T *b, T *d, 
 // x += P xc
 template <typename T>
 void prolong_add(const CsrView &P, const T *val, const T *xc, T *x, hipStream_t s);
+// the same residual and Chebyshev step on the field-block layout of level 0, whose
+// vectors are interleaved by field (off_r + 4 j + f); with x_out_fm set the new
+// iterate is written there in field-major order (off_r + f N_r + j) instead of x_out
+template <typename T>
+void fb_residual(const FieldBlockView &A, const T *val, const T *x, const T *b, T *y, hipStream_t s);
+template <typename T>
+void fb_cheb_step(const FieldBlockView &A, const T *val, const T *x_in, const T *b, T *d, T *x_out, T *x_out_fm,
+                  double c1, double c2, hipStream_t s);
+// field-major vector -> interleaved by field (level-0 order), with a type change
+template <typename TA, typename TB>
+void to_fields4(int64_t Ni, int64_t Ne, const TA *a, TB *b, hipStream_t s);
 template <typename TA, typename TB>
 void convert(int64_t n, const TA *a, TB *b, hipStream_t s);
 void coarse_solve(int64_t n, const int32_t *comp, const int32_t *cloc, const int32_t *cmem, const int64_t *cstart,

@@ -201,6 +201,127 @@ __global__ void __launch_bounds__(TPB) k_prolong_add(const int64_t *__restrict__
     stream_rows<T, T, A>(rowptr, col, val, xc, blk, nblk, e);
 }
 
+// ---------------------------------------------------------------- field-block stream (level 0)
+// Level 0 keeps its vectors interleaved by field: the value of field f at vertex j
+// of region r sits at off_r + 4 j + f, so one vertex's four fields are one 16- (or
+// 32-) byte word.  Block b owns the block rows (region vertices) blk[b]..blk[b+1]-1
+// of one region, whose entries (at most FB_CAP) are contiguous.  Phase 1: each
+// thread takes entries tid + u*TPB, loads the column once, the four field values
+// side by side and the four x values of that vertex as one vector gather, and
+// stages the four products in LDS.  Phase 2: four threads per block row, one per
+// field, sum the row's products in entry order (the scalar stream's order, so the
+// sums match it bit for bit) and hand them to the epilogue with the interleaved
+// index and, for output in the solver's order, the field-major one off_r + f N_r + j.
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
+template <typename T>
+__device__ inline void load4(const T *__restrict__ p, T (&v)[4], bool streaming) {
+    if constexpr (std::is_same<T, float>::value) {
+        const f32x4 w = streaming ? __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(p))
+                                  : *reinterpret_cast<const f32x4 *>(p);
+        v[0] = w.x; v[1] = w.y; v[2] = w.z; v[3] = w.w;
+    } else {
+        const f64x2 w0 = streaming ? __builtin_nontemporal_load(reinterpret_cast<const f64x2 *>(p))
+                                   : *reinterpret_cast<const f64x2 *>(p);
+        const f64x2 w1 = streaming ? __builtin_nontemporal_load(reinterpret_cast<const f64x2 *>(p) + 1)
+                                   : *(reinterpret_cast<const f64x2 *>(p) + 1);
+        v[0] = w0.x; v[1] = w0.y; v[2] = w1.x; v[3] = w1.y;
+    }
+}
+
+template <typename T, typename A, class Epi>
+__device__ inline void stream_field_blocks(const FieldBlockView &fb, const T *__restrict__ val,
+                                           const T *__restrict__ x, Epi &epi) {
+    constexpr int PER = FB_CAP / TPB;
+    __shared__ A prod[4][FB_CAP];
+    const int lb = int(blockIdx.x);
+    if (lb >= fb.nblk) return;
+    const int32_t v0 = fb.blk[lb], v1 = fb.blk[lb + 1];
+    const bool ext = v0 >= fb.Ni;                    // blocks never straddle the regions
+    const int64_t Nr = ext ? fb.Ne : fb.Ni;
+    const int64_t base = ext ? 4 * fb.Ni : 0;        // first DOF of the region
+    const int32_t vfirst = ext ? int32_t(fb.Ni) : 0; // first block row of the region
+    const int64_t k0 = fb.rowptr[v0];
+    const int n = int(fb.rowptr[v1] - k0);
+    const T *xr = x + base;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int i = threadIdx.x + u * TPB;
+        if (i < n) {
+            const int32_t c = __builtin_nontemporal_load(fb.col + k0 + i);
+            T v[4], xv[4];
+            load4<T>(val + 4 * (k0 + i), v, true);
+            load4<T>(xr + 4 * int64_t(c), xv, false);
+#pragma unroll
+            for (int f = 0; f < 4; ++f) prod[f][i] = A(v[f]) * A(xv[f]);
+        }
+    }
+    __syncthreads();
+    const int f = int(threadIdx.x) & 3;
+    for (int32_t row = v0 + int32_t(threadIdx.x >> 2); row < v1; row += TPB / 4) {
+        const int a = int(fb.rowptr[row] - k0), b = int(fb.rowptr[row + 1] - k0);
+        A sum = A(0);
+        for (int k = a; k < b; ++k) sum += prod[f][k];
+        const int64_t j = row - vfirst;
+        epi(int32_t(base + 4 * j + f), int32_t(base + f * Nr + j), sum);
+    }
+}
+
+template <typename T, typename A>
+struct FbResidual {
+    const T *b;
+    T *y;
+    __device__ void operator()(int32_t i, int32_t, A s) const { y[i] = T(A(b[i]) - s); }
+};
+
+// Chebyshev step; with xout_fm set the new iterate goes there in field-major order
+template <typename T, typename A>
+struct FbCheb {
+    const T *xin, *b;
+    T *d, *xout, *xout_fm;
+    A c1, c2;
+    bool use_d;
+    __device__ void operator()(int32_t i, int32_t ifm, A s) const {
+        const A r = A(b[i]) - s;
+        const A dn = (use_d ? c1 * A(d[i]) : A(0)) + c2 * r;
+        d[i] = T(dn);
+        if (xout_fm)
+            xout_fm[ifm] = T(A(xin[i]) + dn);
+        else
+            xout[i] = T(A(xin[i]) + dn);
+    }
+};
+
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_fb_residual(FieldBlockView fb, const T *__restrict__ val,
+                                                     const T *__restrict__ x, const T *__restrict__ b,
+                                                     T *__restrict__ y) {
+    using A = typename Acc<T>::type;
+    FbResidual<T, A> e{b, y};
+    stream_field_blocks<T, A>(fb, val, x, e);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_fb_cheb(FieldBlockView fb, const T *__restrict__ val,
+                                                 const T *__restrict__ xin, const T *__restrict__ b,
+                                                 T *__restrict__ d, T *xout, T *xout_fm, double c1, double c2) {
+    using A = typename Acc<T>::type;
+    FbCheb<T, A> e{xin, b, d, xout, xout_fm, A(c1), A(c2), c1 != 0.0};
+    stream_field_blocks<T, A>(fb, val, xin, e);
+}
+
+// field-major (the solver's order) to interleaved-by-field, with a type change
+template <typename TA, typename TB>
+__global__ void k_to_fields4(int64_t Ni, int64_t Ne, const TA *__restrict__ a, TB *__restrict__ b) {
+    const int64_t n = 4 * (Ni + Ne);
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
+        const bool ext = i >= 4 * Ni;
+        const int64_t base = ext ? 4 * Ni : 0, Nr = ext ? Ne : Ni;
+        const int64_t l = i - base;
+        b[i] = TB(a[base + (l & 3) * Nr + (l >> 2)]);
+    }
+}
+
 template <typename TA, typename TB>
 __global__ void k_convert(int64_t n, const TA *__restrict__ a, TB *__restrict__ b) {
     for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
@@ -377,6 +498,33 @@ void cheb_step(const CsrView &A, const T *val, const T *x_in, const T *b, T *d, 
 }
 
 template <typename T>
+void fb_residual(const FieldBlockView &A, const T *val, const T *x, const T *b, T *y, hipStream_t s) {
+    if (A.nblk == 0) return;
+    hipLaunchKernelGGL((k_fb_residual<T>), dim3(block_grid(A.nblk)), dim3(TPB), 0, s, A, val, x, b, y);
+}
+
+template <typename T>
+void fb_cheb_step(const FieldBlockView &A, const T *val, const T *x_in, const T *b, T *d, T *x_out, T *x_out_fm,
+                  double c1, double c2, hipStream_t s) {
+    const int64_t n = 4 * (A.Ni + A.Ne);
+    if (n == 0) return;
+    if (!x_in) {
+        if (x_out_fm) throw Error{KNP_E_STATE, "a first Chebyshev step cannot write field-major output"};
+        hipLaunchKernelGGL((k_cheb_first<T>), dim3(stream_grid(n)), dim3(TPB), 0, s, n, b, d, x_out, c2);
+        return;
+    }
+    hipLaunchKernelGGL((k_fb_cheb<T>), dim3(block_grid(A.nblk)), dim3(TPB), 0, s, A, val, x_in, b, d, x_out,
+                       x_out_fm, c1, c2);
+}
+
+template <typename TA, typename TB>
+void to_fields4(int64_t Ni, int64_t Ne, const TA *a, TB *b, hipStream_t s) {
+    const int64_t n = 4 * (Ni + Ne);
+    if (n == 0) return;
+    hipLaunchKernelGGL((k_to_fields4<TA, TB>), dim3(stream_grid(n)), dim3(TPB), 0, s, Ni, Ne, a, b);
+}
+
+template <typename T>
 void prolong_add(const CsrView &P, const T *val, const T *xc, T *x, hipStream_t s) {
     if (P.nblk == 0) return;
     hipLaunchKernelGGL((k_prolong_add<T>), dim3(block_grid(P.nblk)), dim3(TPB), 0, s, P.rowptr, P.col, val, xc, P.blk,
@@ -454,6 +602,16 @@ template void cheb_step<double>(const CsrView &, const double *, const double *,
                                 double, double, hipStream_t);
 template void cheb_step<float>(const CsrView &, const float *, const float *, const float *, float *, float *, double,
                                double, hipStream_t);
+template void fb_residual<double>(const FieldBlockView &, const double *, const double *, const double *, double *,
+                                  hipStream_t);
+template void fb_residual<float>(const FieldBlockView &, const float *, const float *, const float *, float *,
+                                 hipStream_t);
+template void fb_cheb_step<double>(const FieldBlockView &, const double *, const double *, const double *, double *,
+                                   double *, double *, double, double, hipStream_t);
+template void fb_cheb_step<float>(const FieldBlockView &, const float *, const float *, const float *, float *,
+                                  float *, float *, double, double, hipStream_t);
+template void to_fields4<double, double>(int64_t, int64_t, const double *, double *, hipStream_t);
+template void to_fields4<double, float>(int64_t, int64_t, const double *, float *, hipStream_t);
 template void prolong_add<double>(const CsrView &, const double *, const double *, double *, hipStream_t);
 template void prolong_add<float>(const CsrView &, const float *, const float *, float *, hipStream_t);
 template void convert<double, float>(int64_t, const double *, float *, hipStream_t);
