@@ -511,9 +511,18 @@ void amg_build(Amg &amg, const HostMesh &m, const std::vector<double> &p0_vals, 
             }
         }
         Csr P = spgemm(DA, T);
+        // release each intermediate once consumed (at ~1e8 unknowns each is 10-70 GB)
+        AF = Csr();
+        DA = Csr();
+        T = Csr();
+        std::vector<int64_t>().swap(srow);
+        std::vector<int32_t>().swap(scol);
         Csr R = transpose(P);
-        Csr AP = spgemm(L.A, P);
-        Csr Ac = spgemm(R, AP);
+        Csr Ac;
+        {
+            Csr AP = spgemm(L.A, P);
+            Ac = spgemm(R, AP);
+        }
         // unit diagonal on the coarse level, absorbed into P and R
         std::vector<double> dc(nc, 1.0);
         for (int64_t c = 0; c < nc; ++c)
