@@ -80,7 +80,39 @@ def run_precision(solver, u0, g0, precision, warmup, steps, log, first_restart, 
             "u": solver.u.cpu().numpy()}
 
 
-def roofline_of(timers):
+# HBM traffic per launch from rocprofv3 counters (FETCH_SIZE, WRITE_SIZE), taken on
+# this workload and calibrated against a plain copy; valid only while the sources
+# that define the kernels and the data layout are the ones the counters were taken on.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_lattice132.json")
+TRAFFIC_SOURCES = ["paper_2403_04491_amd/csrc/linalg.hip", "paper_2403_04491_amd/csrc/knp_internal.h",
+                   "paper_2403_04491_amd/csrc/api.cpp", "paper_2403_04491_amd/csrc/amg.cpp",
+                   "paper_2403_04491_amd/csrc/solver.cpp"]
+
+
+def source_digests():
+    import hashlib
+    out = {}
+    for rel in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            out[rel] = hashlib.sha256(fh.read()).hexdigest()
+    return out
+
+
+def measured_traffic(kernel, precision):
+    """Calibrated HBM bytes per launch of `kernel`, or None if not measured on the
+    current sources."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("sources_sha256") != source_digests():
+        return None
+    k = rec.get("kernels", {}).get(precision, {}).get(kernel)
+    return None if k is None else k.get("bytes_per_launch")
+
+
+def roofline_of(timers, precision=None):
     best = None
     for name in ("spmv_A", "cheb_L0", "resid_L0"):
         t = timers[name]
@@ -93,7 +125,8 @@ def roofline_of(timers):
     avg_s = t["total_ms"] / t["launches"] * 1e-3
     achieved = per_launch_bytes / avg_s / 1e9
     return best, {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                  "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                  "frac": round(achieved / PEAK_HBM_GBS, 4),
+                  "traffic": measured_traffic(best, precision) if precision else None,
                   "kernel": best, "bytes_per_launch": per_launch_bytes,
                   "avg_launch_us": round(avg_s * 1e6, 2), "launches": t["launches"]}
 
@@ -421,7 +454,7 @@ def main():
         runs[name] = run_precision(solver, u0, g0, prec, args.warmup, args.steps, log, args.first_restart,
                                    amg_kw)
     head = runs.get("fp32_amg") or runs["fp64"]
-    kernel, roof = roofline_of(head["timers"])
+    kernel, roof = roofline_of(head["timers"], "fp32_amg" if "fp32_amg" in runs else "fp64")
     extra = {}
     if "fp64" in runs and "fp32_amg" in runs:
         extra["fp32_amg_vs_fp64_final_step_rel_err"] = block_errors(info, runs["fp32_amg"]["u"], runs["fp64"]["u"])

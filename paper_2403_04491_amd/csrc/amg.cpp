@@ -358,34 +358,6 @@ void upload_field_blocks(DevFieldBlock &fb, const HostMesh &m, const std::vector
     hip_check(hipStreamSynchronize(s), "field-block upload");
 }
 
-// Level 0's vectors are interleaved by field, so the prolongation's rows and the
-// restriction's columns move from off_r + f N_r + j to off_r + 4 j + f.
-void interleave_level0_transfer(Csr &P, Csr &R, const HostMesh &m) {
-    const int64_t N = m.N;
-    std::vector<int32_t> to4(N);
-    for (int r = 0; r < 2; ++r)
-        for (int f = 0; f < 4; ++f)
-            for (int64_t j = 0; j < m.Nr[r]; ++j) to4[m.off[r] + f * m.Nr[r] + j] = int32_t(m.off[r] + 4 * j + f);
-    for (auto &c : R.col) c = to4[c];
-    Csr Q;
-    Q.nrows = P.nrows;
-    Q.ncols = P.ncols;
-    Q.rowptr.assign(N + 1, 0);
-    for (int64_t i = 0; i < N; ++i) Q.rowptr[to4[i] + 1] = P.rowptr[i + 1] - P.rowptr[i];
-    for (int64_t i = 0; i < N; ++i) Q.rowptr[i + 1] += Q.rowptr[i];
-    Q.col.resize(P.col.size());
-    Q.val.resize(P.val.size());
-#pragma omp parallel for schedule(static)
-    for (int64_t i = 0; i < N; ++i) {
-        int64_t o = Q.rowptr[to4[i]];
-        for (int64_t k = P.rowptr[i]; k < P.rowptr[i + 1]; ++k, ++o) {
-            Q.col[o] = P.col[k];
-            Q.val[o] = P.val[k];
-        }
-    }
-    P = std::move(Q);
-}
-
 }  // namespace
 
 void amg_build(Amg &amg, const HostMesh &m, const std::vector<double> &p0_vals, const std::vector<double> &near_null,
@@ -394,27 +366,36 @@ void amg_build(Amg &amg, const HostMesh &m, const std::vector<double> &p0_vals, 
     amg.fp32 = o.precision == 1;
     amg.degree = std::max(1, o.cheb_degree);
     amg.ratio = o.cheb_ratio;
-    // P_0 in CSR: per (region, field) the scalar pattern of the region
+    // P_0 in CSR, in the solver's order (DOF off_r + 4 j + f): per region the scalar
+    // pattern of the region for each field.  p0_vals and near_null come in ABI order
+    // (block by block: region r, field f, then the pattern row by row).
     Csr A;
     A.nrows = A.ncols = m.N;
     A.rowptr.assign(m.N + 1, 0);
     for (int r = 0; r < 2; ++r)
-        for (int f = 0; f < 4; ++f)
-            for (int64_t j = 0; j < m.Nr[r]; ++j)
-                A.rowptr[m.off[r] + f * m.Nr[r] + j + 1] = m.prow[r][j + 1] - m.prow[r][j];
+        for (int64_t j = 0; j < m.Nr[r]; ++j)
+            for (int f = 0; f < 4; ++f) A.rowptr[m.off[r] + 4 * j + f + 1] = m.prow[r][j + 1] - m.prow[r][j];
     for (int64_t i = 0; i < m.N; ++i) A.rowptr[i + 1] += A.rowptr[i];
     A.col.resize(A.rowptr[m.N]);
-    for (int r = 0; r < 2; ++r)
-        for (int f = 0; f < 4; ++f) {
-            const int64_t base = m.off[r] + f * m.Nr[r];
+    A.val.resize(A.rowptr[m.N]);
+    std::vector<double> B(m.N);
+    {
+        const int64_t nnz0 = m.prow[0][m.Nr[0]], nnz1 = m.prow[1][m.Nr[1]];
+        const int64_t pbase[2] = {0, 4 * nnz0}, nnzr[2] = {nnz0, nnz1};
+        for (int r = 0; r < 2; ++r) {
 #pragma omp parallel for schedule(static)
-            for (int64_t j = 0; j < m.Nr[r]; ++j) {
-                int64_t o2 = A.rowptr[base + j];
-                for (int64_t k = m.prow[r][j]; k < m.prow[r][j + 1]; ++k) A.col[o2++] = int32_t(base + m.pcol[r][k]);
-            }
+            for (int64_t j = 0; j < m.Nr[r]; ++j)
+                for (int f = 0; f < 4; ++f) {
+                    const int64_t i = m.off[r] + 4 * j + f;
+                    int64_t o2 = A.rowptr[i];
+                    for (int64_t k = m.prow[r][j]; k < m.prow[r][j + 1]; ++k, ++o2) {
+                        A.col[o2] = int32_t(m.off[r] + 4 * int64_t(m.pcol[r][k]) + f);
+                        A.val[o2] = p0_vals[pbase[r] + f * nnzr[r] + k];
+                    }
+                    B[i] = near_null[m.off[r] + f * m.Nr[r] + j];
+                }
         }
-    A.val = p0_vals;
-    std::vector<double> B = near_null;
+    }
 
     std::vector<HostLevel> H;
     const int max_levels = std::max(1, o.max_levels);
@@ -435,6 +416,20 @@ void amg_build(Amg &amg, const HostMesh &m, const std::vector<double> &p0_vals, 
         if (double(nc) > 0.85 * double(n)) {   // coarsening stalled: make this the coarsest
             H.push_back(std::move(L));
             break;
+        }
+        if (H.empty()) {
+            // Level 0 is in the solver's order (fields side by side), but P_0 couples no
+            // two fields, so each aggregate lies in one (region, field) block.  Number
+            // the aggregates block by block, keeping their order within a block, so
+            // that every coarser level has each field's unknowns contiguous.
+            std::vector<int32_t> blk_of(nc, 0);
+            for (int64_t i = 0; i < n; ++i) blk_of[agg[i]] = int32_t((i >= m.off[1] ? 4 : 0) + (i & 3));
+            std::vector<int64_t> start(9, 0);
+            for (int64_t c = 0; c < nc; ++c) start[blk_of[c] + 1]++;
+            for (int q = 0; q < 8; ++q) start[q + 1] += start[q];
+            std::vector<int32_t> renum(nc);
+            for (int64_t c = 0; c < nc; ++c) renum[c] = int32_t(start[blk_of[c]]++);
+            for (int64_t i = 0; i < n; ++i) agg[i] = renum[agg[i]];
         }
         // tentative prolongator from B
         std::vector<double> bn(nc, 0.0);
@@ -617,12 +612,10 @@ void amg_build(Amg &amg, const HostMesh &m, const std::vector<double> &p0_vals, 
         amg.level_nnz.push_back(H[l].A.nnz());
         const bool last = l + 1 == H.size();
         if (!last) {
-            if (l == 0) {
+            if (l == 0)
                 upload_field_blocks(L->fb, m, p0_vals, f32, s);
-                interleave_level0_transfer(H[0].P, H[0].R, m);
-            } else {
+            else
                 L->A.upload(H[l].A, f32, s);
-            }
             L->P.upload(H[l].P, f32, s);
             L->R.upload(H[l].R, f32, s);
         }
@@ -733,16 +726,12 @@ T *vcycle_level(Amg &amg, size_t l, const T *b, hipStream_t s, Timers *tm, T *ou
     const double mat = fbl ? double(L->fb.nnz) * (4.0 * vb + 4.0) + 8.0 * double(L->fb.nv + 1)
                            : double(L->A.nnz) * (vb + 4.0) + 8.0 * double(n + 1);
     Timers *t0 = (l == 0) ? tm : nullptr;
-    // on level 0 the final step (xout == out) writes the field-major output directly
     auto cheb = [&](const T *xin, T *xout, double c1, double c2) {
         hipEvent_t e = t0 ? t0->begin(KNP_TIMER_CHEB_L0, s) : nullptr;
-        if (fbl) {
-            const bool to_out = out && xout == out;
-            launch::fb_cheb_step<T>(L->fb.view(), av, xin, b, d, to_out ? nullptr : xout, to_out ? out : nullptr, c1,
-                                    c2, s);
-        } else {
+        if (fbl)
+            launch::fb_cheb_step<T>(L->fb.view(), av, xin, b, d, xout, c1, c2, s);
+        else
             launch::cheb_step<T>(L->A.view(), av, xin, b, d, xout, c1, c2, s);
-        }
         if (t0) {
             const double bytes = xin ? mat + vb * double(n) * (c1 != 0.0 ? 5.0 : 4.0) : 3.0 * vb * double(n);
             t0->end(KNP_TIMER_CHEB_L0, e, bytes, s);
@@ -783,26 +772,15 @@ T *vcycle_level(Amg &amg, size_t l, const T *b, hipStream_t s, Timers *tm, T *ou
 void amg_vcycle(Amg &amg, const double *v, void *z, hipStream_t s, Timers *tm) {
     Level *L0 = amg.levels[0];
     const int64_t n = L0->n;
-    // with a coarser level, level 0 runs in the field-block layout: its right-hand
-    // side is v interleaved by field; the last smoothing step writes z field-major
-    const bool fbl = amg.levels.size() > 1;
     hipEvent_t e = tm ? tm->begin(KNP_TIMER_VCYCLE, s) : nullptr;
     if (amg.fp32) {
-        if (fbl)
-            launch::to_fields4<double, float>(L0->fb.Ni, L0->fb.Ne, v, L0->b32.p, s);
-        else
-            launch::convert<double, float>(n, v, L0->b32.p, s);
+        launch::convert<double, float>(n, v, L0->b32.p, s);
         float *zf = static_cast<float *>(z);
         float *x = vcycle_level<float>(amg, 0, L0->b32.p, s, tm, zf);
         if (x != zf) hip_check(hipMemcpyAsync(z, x, size_t(n) * sizeof(float), hipMemcpyDeviceToDevice, s), "copy");
     } else {
         double *zd = static_cast<double *>(z);
-        const double *b = v;
-        if (fbl) {
-            launch::to_fields4<double, double>(L0->fb.Ni, L0->fb.Ne, v, L0->b64.p, s);
-            b = L0->b64.p;
-        }
-        double *x = vcycle_level<double>(amg, 0, b, s, tm, zd);
+        double *x = vcycle_level<double>(amg, 0, v, s, tm, zd);
         if (x != zd) hip_check(hipMemcpyAsync(z, x, size_t(n) * sizeof(double), hipMemcpyDeviceToDevice, s), "copy");
     }
     if (tm) tm->end(KNP_TIMER_VCYCLE, e, 0.0, s);

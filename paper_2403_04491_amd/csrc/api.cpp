@@ -326,17 +326,49 @@ knp_status knp_mesh_upload(knp_ctx *c, int dim, int64_t n_vert, const double *xy
                 c->d_cgcol.alloc(col.size());
                 c->d_cgcol.upload(col, s);
             }
-            c->d_rowptr.alloc(h.rowptr.size());
-            c->d_rowptr.upload(h.rowptr, s);
-            c->d_colidx.alloc(h.colidx.size());
-            c->d_colidx.upload(h.colidx, s);
-            c->d_diag.alloc(h.diag_pos.size());
-            c->d_diag.upload(h.diag_pos, s);
+            // storage order: by vertex, four fields side by side (one vertex's unknowns
+            // share a cache line in every gather of x)
             {
-                std::vector<int32_t> b = row_blocks(h.rowptr.data(), h.N);
+                const int64_t N = h.N;
+                c->int2ext.resize(N);
+                c->ext2int.resize(N);
+                for (int r = 0; r < 2; ++r)
+                    for (int f = 0; f < 4; ++f)
+                        for (int64_t j = 0; j < h.Nr[r]; ++j) {
+                            const int64_t e = h.off[r] + f * h.Nr[r] + j, i = h.off[r] + 4 * j + f;
+                            c->int2ext[i] = int32_t(e);
+                            c->ext2int[e] = int32_t(i);
+                        }
+                c->rowptr_s.assign(N + 1, 0);
+                for (int64_t i = 0; i < N; ++i)
+                    c->rowptr_s[i + 1] = c->rowptr_s[i] + (h.rowptr[c->int2ext[i] + 1] - h.rowptr[c->int2ext[i]]);
+                c->rstart.resize(N);
+                for (int64_t i = 0; i < N; ++i) c->rstart[c->int2ext[i]] = c->rowptr_s[i];
+                std::vector<int32_t> cols(std::max<int64_t>(1, h.nnz));
+#pragma omp parallel for schedule(static)
+                for (int64_t i = 0; i < N; ++i) {
+                    const int64_t R = c->int2ext[i], a = h.rowptr[R], len = h.rowptr[R + 1] - a, o = c->rowptr_s[i];
+                    for (int64_t q = 0; q < len; ++q) cols[o + q] = c->ext2int[h.colidx[a + q]];
+                }
+                std::vector<int64_t> diag(N);
+                for (int64_t R = 0; R < N; ++R) diag[R] = c->rstart[R] + (h.diag_pos[R] - h.rowptr[R]);
+                c->d_rowptr.alloc(h.rowptr.size());
+                c->d_rowptr.upload(h.rowptr, s);
+                c->d_rowptr_s.alloc(c->rowptr_s.size());
+                c->d_rowptr_s.upload(c->rowptr_s, s);
+                c->d_rstart.alloc(std::max<int64_t>(1, N));
+                c->d_rstart.upload(c->rstart, s);
+                c->d_int2ext.alloc(std::max<int64_t>(1, N));
+                c->d_int2ext.upload(c->int2ext, s);
+                c->d_colidx.alloc(cols.size());
+                c->d_colidx.upload(cols, s);
+                c->d_diag.alloc(std::max<int64_t>(1, N));
+                c->d_diag.upload(diag, s);
+                std::vector<int32_t> b = row_blocks(c->rowptr_s.data(), N);
                 c->nblkA = int64_t(b.size()) - 1;
                 c->d_blkA.alloc(b.size());
                 c->d_blkA.upload(b, s);
+                hip_check(hipStreamSynchronize(s), "system upload");
             }
             c->d_vals.alloc(h.nnz);
             c->d_sc.alloc(h.N);
@@ -472,14 +504,16 @@ knp_status knp_assemble_step(knp_ctx *c, double t_n, double dt, const double *u_
         auto matrix_and_rhs = [&](bool force_static) {
             if (force_static || dt != c->dt_static) {
                 for (int r = 0; r < 2; ++r)
-                    launch::assemble_static(c->region(r), ma, p, c->d_rowptr.p, c->d_vals.p, c->d_sc.p, h.pin_dof, s);
+                    launch::assemble_static(c->region(r), ma, p, c->d_rowptr.p, c->d_rstart.p, c->d_vals.p, c->d_sc.p,
+                                            h.pin_dof, s);
                 c->dt_static = dt;
             }
             for (int r = 0; r < 2; ++r)
-                launch::assemble_dynamic(c->region(r), ma, p, c->d_rowptr.p, c->d_vals.p, c->d_sc.p, u_prev, f_out,
-                                         h.pin_dof, s);
+                launch::assemble_dynamic(c->region(r), ma, p, c->d_rowptr.p, c->d_rstart.p, c->d_vals.p, c->d_sc.p,
+                                         u_prev, f_out, h.pin_dof, s);
             launch::assemble_membrane(ga, ma, p, h.Nr[0], h.Nr[1], c->d_prow[0].p, c->d_prow[1].p, c->d_rowptr.p,
-                                      c->d_colidx.p, c->d_vals.p, c->d_sc.p, c->d_gcoef.p, f_out, s);
+                                      c->d_rstart.p, c->d_colidx.p, c->d_int2ext.p, c->d_vals.p, c->d_sc.p,
+                                      c->d_gcoef.p, f_out, s);
         };
         matrix_and_rhs(false);
         c->tm.end(KNP_TIMER_ASSEMBLY, t0, c->assembly_bytes, s);
@@ -502,7 +536,7 @@ knp_status knp_assemble_step(knp_ctx *c, double t_n, double dt, const double *u_
                         const int64_t n = h.prow[r][j + 1] - h.prow[r][j];
                         const int64_t len = h.rowptr[row + 1] - h.rowptr[row];
                         const int64_t g = len - (f < 3 ? 2 : 4) * n;
-                        const int64_t seg = h.rowptr[row] + (r == 0 ? 0 : g) + (f < 3 ? 0 : 3 * n);
+                        const int64_t seg = c->rstart[row] + (r == 0 ? 0 : g) + (f < 3 ? 0 : 3 * n);
                         for (int64_t q = 0; q < n; ++q) c->p0_vals[o++] = vals[seg + q];
                     }
             c->near_null.resize(h.N);
@@ -583,27 +617,31 @@ knp_status knp_apply(knp_ctx *c, int which, const double *x, double *y) {
         need_device(c);
         if (!c->assembled) return fail(c, KNP_E_STATE, "no assembled system");
         if (!x || !y) return fail(c, KNP_E_ARG, "NULL vector");
+        if (which < 0 || which > 2) return fail(c, KNP_E_ARG, "which must be 0, 1 or 2");
+        if (which == 1 && !c->amg.ready) return fail(c, KNP_E_STATE, "knp_amg_setup has not been called");
         hip_check(hipSetDevice(c->device), "set device");
+        const int64_t N = c->hm.N;
+        hipStream_t s = c->stream;
+        double *xi = c->w.p, *yi = c->bh.p;   // solver-order copies of x and y
+        launch::to_internal(N, c->d_int2ext.p, x, nullptr, xi, 2, s);
         if (which == 0) {
-            apply_operator(c, false, x, y);
+            apply_operator(c, false, xi, yi);
         } else if (which == 1) {
-            if (!c->amg.ready) return fail(c, KNP_E_STATE, "knp_amg_setup has not been called");
             if (c->amg.fp32) {
                 knp::DArray<float> z;
-                z.alloc(c->hm.N);
-                amg_vcycle(c->amg, x, z.p, c->stream, &c->tm);
-                launch::convert<float, double>(c->hm.N, z.p, y, c->stream);
-                hip_check(hipStreamSynchronize(c->stream), "apply");
+                z.alloc(N);
+                amg_vcycle(c->amg, xi, z.p, s, &c->tm);
+                launch::convert<float, double>(N, z.p, yi, s);
+                hip_check(hipStreamSynchronize(s), "apply");
             } else {
-                amg_vcycle(c->amg, x, y, c->stream, &c->tm);
+                amg_vcycle(c->amg, xi, yi, s, &c->tm);
             }
-        } else if (which == 2) {
-            ensure_transpose(c);
-            apply_operator(c, true, x, y);
         } else {
-            return fail(c, KNP_E_ARG, "which must be 0, 1 or 2");
+            ensure_transpose(c);
+            apply_operator(c, true, xi, yi);
         }
-        hip_check(hipStreamSynchronize(c->stream), "apply");
+        launch::to_external(N, c->d_int2ext.p, yi, nullptr, y, 2, s);
+        hip_check(hipStreamSynchronize(s), "apply");
         return KNP_OK;
     });
 }
@@ -624,8 +662,7 @@ knp_status knp_get_values(knp_ctx *c, double *vals) {
         need_device(c);
         if (!c->assembled) return fail(c, KNP_E_STATE, "no assembled system");
         if (!vals) return fail(c, KNP_E_ARG, "NULL output");
-        hip_check(hipMemcpyAsync(vals, c->d_vals.p, sizeof(double) * c->hm.nnz, hipMemcpyDeviceToDevice, c->stream),
-                  "copy");
+        launch::rows_to_external(c->hm.N, c->d_rowptr.p, c->d_rstart.p, c->d_vals.p, vals, c->stream);
         hip_check(hipStreamSynchronize(c->stream), "sync");
         return KNP_OK;
     });

@@ -10,6 +10,8 @@
 //   int prod lambda_a^{p_a} = m! |T| prod p_a! / (m + sum p_a)!.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "fem_device.h"
 #include "knp_internal.h"
 
@@ -112,7 +114,8 @@ __global__ void k_membrane_coef(GammaArgs g, PhysArgs p, int64_t Ni, int64_t Ne,
 // c_r^k rows, own block: M + tau_k A;  phi_r row, c_r^k blocks: z_k tau_k A.
 template <int D>
 __global__ void __launch_bounds__(BLK) k_static(RegionArgs ra, MeshArgs ma, PhysArgs p,
-                                                const int64_t *__restrict__ rowptr, double *__restrict__ vals,
+                                                const int64_t *__restrict__ rowptr,
+                                                const int64_t *__restrict__ rstart, double *__restrict__ vals,
                                                 const double *__restrict__ sc, int64_t pin_dof) {
     __shared__ double sA[MAXN][BLK];
     __shared__ double sM[MAXN][BLK];
@@ -149,8 +152,8 @@ __global__ void __launch_bounds__(BLK) k_static(RegionArgs ra, MeshArgs ma, Phys
     const int32_t *pc = ra.pcol + p0;
     for (int k = 0; k < 3; ++k) {
         const int64_t row = ra.off + k * Nr + j;
-        const int64_t rp = rowptr[row];
-        const int gq = int(rowptr[row + 1] - rp) - 2 * n;
+        const int64_t rp = rstart[row];
+        const int gq = int(rowptr[row + 1] - rowptr[row]) - 2 * n;
         const int64_t seg = rp + (ra.r == 0 ? 0 : gq);
         const double sr = sc[row];
         for (int q = 0; q < n; ++q) {
@@ -159,8 +162,8 @@ __global__ void __launch_bounds__(BLK) k_static(RegionArgs ra, MeshArgs ma, Phys
         }
     }
     const int64_t row = ra.off + 3 * Nr + j;
-    const int64_t rp = rowptr[row];
-    const int gq = int(rowptr[row + 1] - rp) - 4 * n;
+    const int64_t rp = rstart[row];
+    const int gq = int(rowptr[row + 1] - rowptr[row]) - 4 * n;
     const int64_t seg0 = rp + (ra.r == 0 ? 0 : gq);
     const double sr = sc[row];
     const bool pinrow = row == pin_dof;
@@ -177,7 +180,8 @@ __global__ void __launch_bounds__(BLK) k_static(RegionArgs ra, MeshArgs ma, Phys
 // A_r^k uses c^{k,n-1} (exact for P1: element mean times the element stiffness).
 template <int D>
 __global__ void __launch_bounds__(BLK) k_dynamic(RegionArgs ra, MeshArgs ma, PhysArgs p,
-                                                 const int64_t *__restrict__ rowptr, double *__restrict__ vals,
+                                                 const int64_t *__restrict__ rowptr,
+                                                 const int64_t *__restrict__ rstart, double *__restrict__ vals,
                                                  const double *__restrict__ sc, const double *__restrict__ u,
                                                  double *__restrict__ f, int64_t pin_dof) {
     __shared__ double sK[3][MAXN][BLK];
@@ -230,8 +234,8 @@ __global__ void __launch_bounds__(BLK) k_dynamic(RegionArgs ra, MeshArgs ma, Phy
     const int64_t phib = ra.off + 3 * Nr;
     for (int k = 0; k < 3; ++k) {
         const int64_t row = ra.off + k * Nr + j;
-        const int64_t rp = rowptr[row];
-        const int gq = int(rowptr[row + 1] - rp) - 2 * n;
+        const int64_t rp = rstart[row];
+        const int gq = int(rowptr[row + 1] - rowptr[row]) - 2 * n;
         const int64_t seg = rp + (ra.r == 0 ? 0 : gq) + n;
         const double sr = sc[row];
         for (int q = 0; q < n; ++q) {
@@ -242,8 +246,8 @@ __global__ void __launch_bounds__(BLK) k_dynamic(RegionArgs ra, MeshArgs ma, Phy
         f[row] = mc[k];
     }
     const int64_t row = phib + j;
-    const int64_t rp = rowptr[row];
-    const int gq = int(rowptr[row + 1] - rp) - 4 * n;
+    const int64_t rp = rstart[row];
+    const int gq = int(rowptr[row + 1] - rowptr[row]) - 4 * n;
     const int64_t seg = rp + (ra.r == 0 ? 0 : gq) + 3 * n;
     const double sr = sc[row];
     const bool pinrow = row == pin_dof;
@@ -270,8 +274,10 @@ template <int D>
 __global__ void __launch_bounds__(MBLK) k_membrane(GammaArgs g, MeshArgs ma, PhysArgs p, int64_t Ni, int64_t Ne,
                                                    const int64_t *__restrict__ prow_i,
                                                    const int64_t *__restrict__ prow_e,
-                                                   const int64_t *__restrict__ rowptr, double *__restrict__ vals,
+                                                   const int64_t *__restrict__ rowptr,
+                                                   const int64_t *__restrict__ rstart, double *__restrict__ vals,
                                                    const int32_t *__restrict__ colidx,
+                                                   const int32_t *__restrict__ int2ext,
                                                    const double *__restrict__ sc, const double *__restrict__ gc,
                                                    double *__restrict__ f) {
     __shared__ double sC[3][MAXN][MBLK];
@@ -342,7 +348,7 @@ __global__ void __launch_bounds__(MBLK) k_membrane(GammaArgs g, MeshArgs ma, Phy
     // phi_q block (membrane neighbours, ascending) is written outright
     for (int k = 0; k < 4; ++k) {
         const int64_t row = offr + k * Nr + j;
-        const int64_t rp = rowptr[row];
+        const int64_t rp = rstart[row];
         const int nb = k < 3 ? 1 : 3;              // blocks preceding phi_r in this row
         const int64_t seg_phi = rp + (r == 0 ? 0 : gn) + int64_t(nb) * n;
         const int64_t seg_q = r == 0 ? rp + int64_t(nb + 1) * n : rp;
@@ -350,12 +356,12 @@ __global__ void __launch_bounds__(MBLK) k_membrane(GammaArgs g, MeshArgs ma, Phy
         for (int q = 0; q < n; ++q) {
             const int64_t pos = seg_phi + q;
             const double add = k < 3 ? sC[k][q][tid] : sS[q][tid];
-            vals[pos] += add * sr * sc[colidx[pos]];
+            vals[pos] += add * sr * sc[int2ext[colidx[pos]]];
         }
         for (int q = 0; q < gn; ++q) {
             const int64_t pos = seg_q + q;
             const double v = k < 3 ? sX[k][q][tid] : sXS[q][tid];
-            vals[pos] = v * sr * sc[colidx[pos]];
+            vals[pos] = v * sr * sc[int2ext[colidx[pos]]];
         }
         f[row] += fg[k];
     }
@@ -383,10 +389,33 @@ __global__ void k_gather(int64_t n, const double *__restrict__ src, const int64_
     if (i < n) dst[i] = src[map[i]];
 }
 
-__global__ void k_scale_vec(int64_t n, const double *__restrict__ x, const double *__restrict__ sc,
-                            double *__restrict__ y, int invert) {
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i < n) y[i] = invert ? x[i] / sc[i] : x[i] * sc[i];
+// Solver order <-> ABI order.  The matrix and every solver vector are stored by
+// vertex with the four fields side by side (internal DOF off_r + 4 j + f); the
+// ABI and the assembly use off_r + f N_r + j.  int2ext maps the first to the
+// second.  mode 0: times sc, 1: divided by sc, 2: plain copy (sc ignored).
+__global__ void k_to_internal(int64_t n, const int32_t *__restrict__ int2ext, const double *__restrict__ x,
+                              const double *__restrict__ sc, double *__restrict__ y, int mode) {
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
+        const int32_t e = int2ext[i];
+        y[i] = mode == 0 ? x[e] * sc[e] : (mode == 1 ? x[e] / sc[e] : x[e]);
+    }
+}
+
+__global__ void k_to_external(int64_t n, const int32_t *__restrict__ int2ext, const double *__restrict__ y,
+                              const double *__restrict__ sc, double *__restrict__ x, int mode) {
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
+        const int32_t e = int2ext[i];
+        x[e] = mode == 0 ? y[i] * sc[e] : (mode == 1 ? y[i] / sc[e] : y[i]);
+    }
+}
+
+// values of each ABI-order row from their storage position
+__global__ void k_rows_to_external(int64_t N, const int64_t *__restrict__ rowptr, const int64_t *__restrict__ rstart,
+                                   const double *__restrict__ src, double *__restrict__ dst) {
+    for (int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; r < N; r += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t a = rowptr[r], len = rowptr[r + 1] - a, b = rstart[r];
+        for (int64_t q = 0; q < len; ++q) dst[a + q] = src[b + q];
+    }
 }
 
 inline unsigned nblocks(int64_t n, int b) { return unsigned((n + b - 1) / b); }
@@ -405,39 +434,40 @@ void membrane_coefficients(const GammaArgs &g, const PhysArgs &p, int64_t Ni, in
 }
 
 void assemble_static(const RegionArgs &ra, const MeshArgs &ma, const PhysArgs &p, const int64_t *rowptr,
-                     double *vals, const double *sc, int64_t pin_dof, hipStream_t s) {
+                     const int64_t *rstart, double *vals, const double *sc, int64_t pin_dof, hipStream_t s) {
     if (ra.Nr == 0) return;
     if (ma.dim == 2)
-        hipLaunchKernelGGL(k_static<2>, dim3(nblocks(ra.Nr, BLK)), dim3(BLK), 0, s, ra, ma, p, rowptr, vals, sc,
-                           pin_dof);
+        hipLaunchKernelGGL(k_static<2>, dim3(nblocks(ra.Nr, BLK)), dim3(BLK), 0, s, ra, ma, p, rowptr, rstart, vals,
+                           sc, pin_dof);
     else
-        hipLaunchKernelGGL(k_static<3>, dim3(nblocks(ra.Nr, BLK)), dim3(BLK), 0, s, ra, ma, p, rowptr, vals, sc,
-                           pin_dof);
+        hipLaunchKernelGGL(k_static<3>, dim3(nblocks(ra.Nr, BLK)), dim3(BLK), 0, s, ra, ma, p, rowptr, rstart, vals,
+                           sc, pin_dof);
 }
 
 void assemble_dynamic(const RegionArgs &ra, const MeshArgs &ma, const PhysArgs &p, const int64_t *rowptr,
-                      double *vals, const double *sc, const double *u_prev, double *f, int64_t pin_dof,
-                      hipStream_t s) {
+                      const int64_t *rstart, double *vals, const double *sc, const double *u_prev, double *f,
+                      int64_t pin_dof, hipStream_t s) {
     if (ra.Nr == 0) return;
     if (ma.dim == 2)
-        hipLaunchKernelGGL(k_dynamic<2>, dim3(nblocks(ra.Nr, BLK)), dim3(BLK), 0, s, ra, ma, p, rowptr, vals, sc,
-                           u_prev, f, pin_dof);
+        hipLaunchKernelGGL(k_dynamic<2>, dim3(nblocks(ra.Nr, BLK)), dim3(BLK), 0, s, ra, ma, p, rowptr, rstart, vals,
+                           sc, u_prev, f, pin_dof);
     else
-        hipLaunchKernelGGL(k_dynamic<3>, dim3(nblocks(ra.Nr, BLK)), dim3(BLK), 0, s, ra, ma, p, rowptr, vals, sc,
-                           u_prev, f, pin_dof);
+        hipLaunchKernelGGL(k_dynamic<3>, dim3(nblocks(ra.Nr, BLK)), dim3(BLK), 0, s, ra, ma, p, rowptr, rstart, vals,
+                           sc, u_prev, f, pin_dof);
 }
 
 void assemble_membrane(const GammaArgs &g, const MeshArgs &ma, const PhysArgs &p, int64_t Ni, int64_t Ne,
-                       const int64_t *prow_i, const int64_t *prow_e, const int64_t *rowptr, const int32_t *colidx,
-                       double *vals, const double *sc, const double *gcoef, double *f, hipStream_t s) {
+                       const int64_t *prow_i, const int64_t *prow_e, const int64_t *rowptr, const int64_t *rstart,
+                       const int32_t *colidx, const int32_t *int2ext, double *vals, const double *sc,
+                       const double *gcoef, double *f, hipStream_t s) {
     if (g.n_gamma == 0) return;
     const unsigned nb = nblocks(2 * g.n_gamma, MBLK);
     if (ma.dim == 2)
         hipLaunchKernelGGL(k_membrane<2>, dim3(nb), dim3(MBLK), 0, s, g, ma, p, Ni, Ne, prow_i, prow_e, rowptr,
-                           vals, colidx, sc, gcoef, f);
+                           rstart, vals, colidx, int2ext, sc, gcoef, f);
     else
         hipLaunchKernelGGL(k_membrane<3>, dim3(nb), dim3(MBLK), 0, s, g, ma, p, Ni, Ne, prow_i, prow_e, rowptr,
-                           vals, colidx, sc, gcoef, f);
+                           rstart, vals, colidx, int2ext, sc, gcoef, f);
 }
 
 void scaling_from_diag(int64_t N, const double *vals, const int64_t *diag_pos, double *sc, hipStream_t s) {
@@ -449,9 +479,25 @@ void gather(int64_t n, const double *src, const int64_t *map, double *dst, hipSt
     hipLaunchKernelGGL(k_gather, dim3(nblocks(n, 256)), dim3(256), 0, s, n, src, map, dst);
 }
 
-void scale_vec(int64_t n, const double *x, const double *sc, double *y, int invert, hipStream_t s) {
+void to_internal(int64_t n, const int32_t *int2ext, const double *x, const double *sc, double *y, int mode,
+                 hipStream_t s) {
     if (n == 0) return;
-    hipLaunchKernelGGL(k_scale_vec, dim3(nblocks(n, 256)), dim3(256), 0, s, n, x, sc, y, invert);
+    hipLaunchKernelGGL(k_to_internal, dim3(std::min<int64_t>(nblocks(n, 256), 8192)), dim3(256), 0, s, n, int2ext, x,
+                       sc, y, mode);
+}
+
+void to_external(int64_t n, const int32_t *int2ext, const double *y, const double *sc, double *x, int mode,
+                 hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_to_external, dim3(std::min<int64_t>(nblocks(n, 256), 8192)), dim3(256), 0, s, n, int2ext, y,
+                       sc, x, mode);
+}
+
+void rows_to_external(int64_t N, const int64_t *rowptr, const int64_t *rstart, const double *src, double *dst,
+                      hipStream_t s) {
+    if (N == 0) return;
+    hipLaunchKernelGGL(k_rows_to_external, dim3(std::min<int64_t>(nblocks(N, 256), 8192)), dim3(256), 0, s, N, rowptr,
+                       rstart, src, dst);
 }
 
 }  // namespace launch

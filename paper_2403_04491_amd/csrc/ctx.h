@@ -36,10 +36,18 @@ struct knp_ctx {
     const double *last_theta = nullptr;
     double last_t = 0.0, last_dt = 0.0;
 
-    // system
-    knp::DArray<int64_t> d_rowptr, d_diag;
-    knp::DArray<int32_t> d_colidx;
-    knp::DArray<double> d_vals, d_sc;
+    // system.  Storage is by vertex with the four fields side by side: storage row
+    // (and solver DOF) off_r + 4 j + f holds ABI row off_r + f N_r + j, with its
+    // entries in the ABI row's order and columns renumbered to storage DOFs.
+    knp::DArray<int64_t> d_rowptr;      // ABI-order row pointers (row lengths for the assembly)
+    knp::DArray<int64_t> d_rowptr_s;    // storage row pointers
+    knp::DArray<int64_t> d_rstart;      // [N] storage start of ABI row R
+    knp::DArray<int64_t> d_diag;        // [N] storage position of ABI row R's diagonal
+    knp::DArray<int32_t> d_int2ext;     // [N] storage DOF -> ABI DOF
+    knp::DArray<int32_t> d_colidx;      // storage columns
+    knp::DArray<double> d_vals, d_sc;   // values in storage order; S in ABI order
+    std::vector<int64_t> rowptr_s, rstart;
+    std::vector<int32_t> int2ext, ext2int;
     knp::DArray<int32_t> d_blkA;
     int64_t nblkA = 0;
     knp::DArray<int32_t> d_flag;
@@ -76,7 +84,7 @@ struct knp_ctx {
         v.nrows = hm.N;
         v.nnz = hm.nnz;
         v.nblk = nblkA;
-        v.rowptr = d_rowptr.p;
+        v.rowptr = d_rowptr_s.p;
         v.col = d_colidx.p;
         v.blk = d_blkA.p;
         return v;

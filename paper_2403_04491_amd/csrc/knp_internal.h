@@ -167,10 +167,8 @@ struct DevCsr {
 // region's scalar pattern (rows and columns by region vertex).  It is stored once
 // per vertex pair with the four field values side by side: block row v is region
 // vertex v (region i first, then region e), its entries index region-local
-// vertices, and vals[4k + f] is the field-f value of entry k.  Level-0 vectors are
-// interleaved by field: (region r, field f, local vertex j) sits at off_r + 4 j + f
-// (the solver's own order is off_r + f N_r + j); the restriction's columns and the
-// prolongation's rows on level 0 are numbered the same way.
+// vertices, and vals[4k + f] is the field-f value of entry k.  Its vectors are in
+// the solver's order, (region r, field f, local vertex j) at off_r + 4 j + f.
 constexpr int FB_CAP = 1024;        // vertex-pair entries per row block (4 products each)
 struct FieldBlockView {
     int64_t nv = 0, nnz = 0, nblk = 0;   // block rows, entries, row blocks
@@ -283,18 +281,27 @@ struct GammaArgs {
 void check_finite(const double *u, int64_t n, int *flag, hipStream_t s);
 void membrane_coefficients(const GammaArgs &g, const PhysArgs &p, int64_t Ni, int64_t Ne, const double *u_prev,
                            double *gates, const double *theta, double *gcoef, hipStream_t s);
+// rowptr: ABI-order row pointers (row lengths); rstart[R]: storage start of ABI row R
 void assemble_static(const RegionArgs &ra, const MeshArgs &ma, const PhysArgs &p,
-                     const int64_t *rowptr, double *vals, const double *sc, int64_t pin_dof,
+                     const int64_t *rowptr, const int64_t *rstart, double *vals, const double *sc, int64_t pin_dof,
                      hipStream_t s);
 void assemble_dynamic(const RegionArgs &ra, const MeshArgs &ma, const PhysArgs &p,
-                      const int64_t *rowptr, double *vals, const double *sc, const double *u_prev,
-                      double *f, int64_t pin_dof, hipStream_t s);
+                      const int64_t *rowptr, const int64_t *rstart, double *vals, const double *sc,
+                      const double *u_prev, double *f, int64_t pin_dof, hipStream_t s);
 void assemble_membrane(const GammaArgs &g, const MeshArgs &ma, const PhysArgs &p, int64_t Ni, int64_t Ne,
-                       const int64_t *prow_i, const int64_t *prow_e, const int64_t *rowptr, const int32_t *colidx,
-                       double *vals, const double *sc, const double *gcoef, double *f, hipStream_t s);
+                       const int64_t *prow_i, const int64_t *prow_e, const int64_t *rowptr, const int64_t *rstart,
+                       const int32_t *colidx, const int32_t *int2ext, double *vals, const double *sc,
+                       const double *gcoef, double *f, hipStream_t s);
+// solver order (off_r + 4 j + f) <-> ABI order (off_r + f N_r + j); int2ext maps the
+// first to the second; mode 0: times sc, 1: divided by sc, 2: plain copy
+void to_internal(int64_t n, const int32_t *int2ext, const double *x, const double *sc, double *y, int mode,
+                 hipStream_t s);
+void to_external(int64_t n, const int32_t *int2ext, const double *y, const double *sc, double *x, int mode,
+                 hipStream_t s);
+void rows_to_external(int64_t N, const int64_t *rowptr, const int64_t *rstart, const double *src, double *dst,
+                      hipStream_t s);
 void scaling_from_diag(int64_t N, const double *vals, const int64_t *diag_pos, double *sc, hipStream_t s);
 void gather(int64_t n, const double *src, const int64_t *map, double *dst, hipStream_t s);
-void scale_vec(int64_t n, const double *x, const double *sc, double *y, int invert, hipStream_t s);
 
 // sparse and dense linear algebra (block-streamed CSR)
 template <typename TM, typename TX, typename TY>
@@ -309,17 +316,12 @@ void cheb_step(const CsrView &A, const T *val, const T *x_in, const T *b, T *d, 
 // x += P xc
 template <typename T>
 void prolong_add(const CsrView &P, const T *val, const T *xc, T *x, hipStream_t s);
-// the same residual and Chebyshev step on the field-block layout of level 0, whose
-// vectors are interleaved by field (off_r + 4 j + f); with x_out_fm set the new
-// iterate is written there in field-major order (off_r + f N_r + j) instead of x_out
+// the same residual and Chebyshev step on the field-block layout of level 0
 template <typename T>
 void fb_residual(const FieldBlockView &A, const T *val, const T *x, const T *b, T *y, hipStream_t s);
 template <typename T>
-void fb_cheb_step(const FieldBlockView &A, const T *val, const T *x_in, const T *b, T *d, T *x_out, T *x_out_fm,
-                  double c1, double c2, hipStream_t s);
-// field-major vector -> interleaved by field (level-0 order), with a type change
-template <typename TA, typename TB>
-void to_fields4(int64_t Ni, int64_t Ne, const TA *a, TB *b, hipStream_t s);
+void fb_cheb_step(const FieldBlockView &A, const T *val, const T *x_in, const T *b, T *d, T *x_out, double c1,
+                  double c2, hipStream_t s);
 template <typename TA, typename TB>
 void convert(int64_t n, const TA *a, TB *b, hipStream_t s);
 void coarse_solve(int64_t n, const int32_t *comp, const int32_t *cloc, const int32_t *cmem, const int64_t *cstart,
@@ -336,7 +338,6 @@ void reduce_partials(int k, int nblk, const double *partial, double *out, hipStr
 void scale_by_inv_norm(int64_t n, const double *w, const double *nrm2, double *v, hipStream_t s);
 void add_scaled(int64_t n, double a, const double *x, double *y, hipStream_t s);   // y += a x
 void axpby(int64_t n, double a, const double *x, double b, double *y, hipStream_t s);
-void vmul(int64_t n, const double *a, const double *b, double *y, hipStream_t s);  // y = a .* b
 void sub(int64_t n, const double *a, const double *b, double *y, hipStream_t s);   // y = a - b
 int reduce_blocks(int64_t n);
 

@@ -210,8 +210,7 @@ __global__ void __launch_bounds__(TPB) k_prolong_add(const int64_t *__restrict__
 // side by side and the four x values of that vertex as one vector gather, and
 // stages the four products in LDS.  Phase 2: four threads per block row, one per
 // field, sum the row's products in entry order (the scalar stream's order, so the
-// sums match it bit for bit) and hand them to the epilogue with the interleaved
-// index and, for output in the solver's order, the field-major one off_r + f N_r + j.
+// sums match it bit for bit) and hand them to the epilogue.
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 
 template <typename T>
@@ -262,64 +261,26 @@ __device__ inline void stream_field_blocks(const FieldBlockView &fb, const T *__
         const int a = int(fb.rowptr[row] - k0), b = int(fb.rowptr[row + 1] - k0);
         A sum = A(0);
         for (int k = a; k < b; ++k) sum += prod[f][k];
-        const int64_t j = row - vfirst;
-        epi(int32_t(base + 4 * j + f), int32_t(base + f * Nr + j), sum);
+        epi(int32_t(base + 4 * (row - vfirst) + f), sum);
     }
 }
-
-template <typename T, typename A>
-struct FbResidual {
-    const T *b;
-    T *y;
-    __device__ void operator()(int32_t i, int32_t, A s) const { y[i] = T(A(b[i]) - s); }
-};
-
-// Chebyshev step; with xout_fm set the new iterate goes there in field-major order
-template <typename T, typename A>
-struct FbCheb {
-    const T *xin, *b;
-    T *d, *xout, *xout_fm;
-    A c1, c2;
-    bool use_d;
-    __device__ void operator()(int32_t i, int32_t ifm, A s) const {
-        const A r = A(b[i]) - s;
-        const A dn = (use_d ? c1 * A(d[i]) : A(0)) + c2 * r;
-        d[i] = T(dn);
-        if (xout_fm)
-            xout_fm[ifm] = T(A(xin[i]) + dn);
-        else
-            xout[i] = T(A(xin[i]) + dn);
-    }
-};
 
 template <typename T>
 __global__ void __launch_bounds__(TPB) k_fb_residual(FieldBlockView fb, const T *__restrict__ val,
                                                      const T *__restrict__ x, const T *__restrict__ b,
                                                      T *__restrict__ y) {
     using A = typename Acc<T>::type;
-    FbResidual<T, A> e{b, y};
+    EpiResidual<T, A> e{b, y};
     stream_field_blocks<T, A>(fb, val, x, e);
 }
 
 template <typename T>
 __global__ void __launch_bounds__(TPB) k_fb_cheb(FieldBlockView fb, const T *__restrict__ val,
                                                  const T *__restrict__ xin, const T *__restrict__ b,
-                                                 T *__restrict__ d, T *xout, T *xout_fm, double c1, double c2) {
+                                                 T *__restrict__ d, T *__restrict__ xout, double c1, double c2) {
     using A = typename Acc<T>::type;
-    FbCheb<T, A> e{xin, b, d, xout, xout_fm, A(c1), A(c2), c1 != 0.0};
+    EpiCheb<T, A> e{xin, b, d, xout, A(c1), A(c2), c1 != 0.0};
     stream_field_blocks<T, A>(fb, val, xin, e);
-}
-
-// field-major (the solver's order) to interleaved-by-field, with a type change
-template <typename TA, typename TB>
-__global__ void k_to_fields4(int64_t Ni, int64_t Ne, const TA *__restrict__ a, TB *__restrict__ b) {
-    const int64_t n = 4 * (Ni + Ne);
-    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
-        const bool ext = i >= 4 * Ni;
-        const int64_t base = ext ? 4 * Ni : 0, Nr = ext ? Ne : Ni;
-        const int64_t l = i - base;
-        b[i] = TB(a[base + (l & 3) * Nr + (l >> 2)]);
-    }
 }
 
 template <typename TA, typename TB>
@@ -435,11 +396,6 @@ __global__ void k_axpby(int64_t n, double a, const double *x, double b, double *
         y[i] = a * x[i] + (b == 0.0 ? 0.0 : b * y[i]);
 }
 
-__global__ void k_vmul(int64_t n, const double *a, const double *b, double *y) {
-    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
-        y[i] = a[i] * b[i];
-}
-
 // operands may alias the output (element-wise)
 __global__ void k_sub(int64_t n, const double *a, const double *b, double *y) {
     for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
@@ -504,24 +460,16 @@ void fb_residual(const FieldBlockView &A, const T *val, const T *x, const T *b, 
 }
 
 template <typename T>
-void fb_cheb_step(const FieldBlockView &A, const T *val, const T *x_in, const T *b, T *d, T *x_out, T *x_out_fm,
-                  double c1, double c2, hipStream_t s) {
+void fb_cheb_step(const FieldBlockView &A, const T *val, const T *x_in, const T *b, T *d, T *x_out, double c1,
+                  double c2, hipStream_t s) {
     const int64_t n = 4 * (A.Ni + A.Ne);
     if (n == 0) return;
     if (!x_in) {
-        if (x_out_fm) throw Error{KNP_E_STATE, "a first Chebyshev step cannot write field-major output"};
         hipLaunchKernelGGL((k_cheb_first<T>), dim3(stream_grid(n)), dim3(TPB), 0, s, n, b, d, x_out, c2);
         return;
     }
-    hipLaunchKernelGGL((k_fb_cheb<T>), dim3(block_grid(A.nblk)), dim3(TPB), 0, s, A, val, x_in, b, d, x_out,
-                       x_out_fm, c1, c2);
-}
-
-template <typename TA, typename TB>
-void to_fields4(int64_t Ni, int64_t Ne, const TA *a, TB *b, hipStream_t s) {
-    const int64_t n = 4 * (Ni + Ne);
-    if (n == 0) return;
-    hipLaunchKernelGGL((k_to_fields4<TA, TB>), dim3(stream_grid(n)), dim3(TPB), 0, s, Ni, Ne, a, b);
+    hipLaunchKernelGGL((k_fb_cheb<T>), dim3(block_grid(A.nblk)), dim3(TPB), 0, s, A, val, x_in, b, d, x_out, c1,
+                       c2);
 }
 
 template <typename T>
@@ -583,10 +531,6 @@ void axpby(int64_t n, double a, const double *x, double b, double *y, hipStream_
     hipLaunchKernelGGL(k_axpby, dim3(stream_grid(n)), dim3(TPB), 0, s, n, a, x, b, y);
 }
 
-void vmul(int64_t n, const double *a, const double *b, double *y, hipStream_t s) {
-    hipLaunchKernelGGL(k_vmul, dim3(stream_grid(n)), dim3(TPB), 0, s, n, a, b, y);
-}
-
 void sub(int64_t n, const double *a, const double *b, double *y, hipStream_t s) {
     hipLaunchKernelGGL(k_sub, dim3(stream_grid(n)), dim3(TPB), 0, s, n, a, b, y);
 }
@@ -607,11 +551,9 @@ template void fb_residual<double>(const FieldBlockView &, const double *, const 
 template void fb_residual<float>(const FieldBlockView &, const float *, const float *, const float *, float *,
                                  hipStream_t);
 template void fb_cheb_step<double>(const FieldBlockView &, const double *, const double *, const double *, double *,
-                                   double *, double *, double, double, hipStream_t);
+                                   double *, double, double, hipStream_t);
 template void fb_cheb_step<float>(const FieldBlockView &, const float *, const float *, const float *, float *,
-                                  float *, float *, double, double, hipStream_t);
-template void to_fields4<double, double>(int64_t, int64_t, const double *, double *, hipStream_t);
-template void to_fields4<double, float>(int64_t, int64_t, const double *, float *, hipStream_t);
+                                  float *, double, double, hipStream_t);
 template void prolong_add<double>(const CsrView &, const double *, const double *, double *, hipStream_t);
 template void prolong_add<float>(const CsrView &, const float *, const float *, float *, hipStream_t);
 template void convert<double, float>(int64_t, const double *, float *, hipStream_t);

@@ -68,8 +68,9 @@ knp_status krylov_solve(knp_ctx *c, bool transpose, const double *b, double *x, 
     ensure_workspace(c, m, z32);
     if (transpose) ensure_transpose(c);
     double *bh = c->bh.p, *yh = c->yh.p, *w = c->w.p;
-    launch::vmul(N, b, c->d_sc.p, bh, s);
-    launch::scale_vec(N, x, c->d_sc.p, yh, 1, s);
+    // into the solver's order and scaling: bh = S b, yh = S^{-1} x
+    launch::to_internal(N, c->d_int2ext.p, b, c->d_sc.p, bh, 0, s);
+    launch::to_internal(N, c->d_int2ext.p, x, c->d_sc.p, yh, 1, s);
     const double bnorm = std::sqrt(dev_dot(c, bh, bh, N));
     knp_solve_info inf{};
     if (!std::isfinite(bnorm)) throw Error{KNP_E_NUMERIC, "NaN or Inf in the right-hand side"};
@@ -197,7 +198,7 @@ knp_status krylov_solve(knp_ctx *c, bool transpose, const double *b, double *x, 
     if (converged) inf.rel_res_est = est;
     inf.its = its;
     inf.restarts = restarts;
-    launch::vmul(N, yh, c->d_sc.p, x, s);
+    launch::to_external(N, c->d_int2ext.p, yh, c->d_sc.p, x, 0, s);   // x = S yh
     hip_check(hipStreamSynchronize(s), "solve sync");
     c->tm.harvest();
     if (info) *info = inf;
@@ -209,17 +210,21 @@ void ensure_transpose(knp_ctx *c) {
     const HostMesh &m = c->hm;
     hipStream_t s = c->stream;
     if (!c->have_T) {
+        // transpose of the stored (solver-order) pattern; perm[p] is the storage
+        // position of the entry that lands at position p of the transpose
         std::vector<int64_t> rpT(m.N + 1, 0), perm(m.nnz);
         std::vector<int32_t> colT(m.nnz);
-        for (int64_t k = 0; k < m.nnz; ++k) rpT[m.colidx[k] + 1]++;
+        for (int64_t k = 0; k < m.nnz; ++k) rpT[c->ext2int[m.colidx[k]] + 1]++;
         for (int64_t i = 0; i < m.N; ++i) rpT[i + 1] += rpT[i];
         std::vector<int64_t> fill(rpT.begin(), rpT.end() - 1);
-        for (int64_t i = 0; i < m.N; ++i)
-            for (int64_t k = m.rowptr[i]; k < m.rowptr[i + 1]; ++k) {
-                const int64_t p = fill[m.colidx[k]]++;
+        for (int64_t i = 0; i < m.N; ++i) {
+            const int64_t R = c->int2ext[i], a = m.rowptr[R], len = m.rowptr[R + 1] - a;
+            for (int64_t q = 0; q < len; ++q) {
+                const int64_t p = fill[c->ext2int[m.colidx[a + q]]]++;
                 colT[p] = int32_t(i);
-                perm[p] = k;
+                perm[p] = c->rowptr_s[i] + q;
             }
+        }
         c->d_rowptrT.alloc(m.N + 1);
         c->d_rowptrT.upload(rpT, s);
         c->d_colT.alloc(m.nnz);

@@ -174,7 +174,7 @@ def test_autograd_function_and_central_differences(grad_case):
 
 def test_solver_stops_at_attainable_accuracy():
     """An adjoint solve asked for 1e-14 (below its ~1e-12 rounding floor) stops
-    with NOCONV long before max_it; at 1e-11 it converges."""
+    with NOCONV by the stall rule, long before max_it; at 1e-11 it converges."""
     from paper_2403_04491_amd import KnpSolver, solve_opts
     case = config_case(4, per_pitch=4, n_steps=2)
     asm = Assembler(case)
@@ -186,9 +186,9 @@ def test_solver_stops_at_attainable_accuracy():
     pd = probe_dofs(asm, case.probes)
     rhs[pd] = 2 * case.dt * traj[2][pd]
     lam = torch.zeros(asm.lay.N, dtype=torch.float64, device=DEV)
-    info, ok = S.ctx.adjoint_solve(T(rhs), lam, solve_opts(rtol=1e-14, restart=400, max_it=4000, reorth=1),
+    info, ok = S.ctx.adjoint_solve(T(rhs), lam, solve_opts(rtol=1e-14, restart=400, max_it=20000, reorth=1),
                                    allow_noconv=True)
-    assert not ok and info.its < 2000 and 1e-14 < info.rel_res < 1e-10
+    assert not ok and info.its < 10000 and 1e-14 < info.rel_res < 1e-10, (info.its, info.rel_res)
     lam.zero_()
     info, ok = S.ctx.adjoint_solve(T(rhs), lam, solve_opts(rtol=1e-11, restart=400, max_it=4000, reorth=1))
     assert ok and info.rel_res <= 1e-11
