@@ -612,10 +612,18 @@ void amg_build(Amg &amg, const HostMesh &m, const std::vector<double> &p0_vals, 
         amg.level_nnz.push_back(H[l].A.nnz());
         const bool last = l + 1 == H.size();
         if (!last) {
-            if (l == 0)
+            if (l == 0) {
                 upload_field_blocks(L->fb, m, p0_vals, f32, s);
-            else
+                // level 0's residual reaches the restriction field-major
+                for (auto &cidx : H[0].R.col) {
+                    const int64_t i = cidx;
+                    const int r = i >= m.off[1] ? 1 : 0;
+                    const int64_t q = i - m.off[r];
+                    cidx = int32_t(m.off[r] + (q & 3) * m.Nr[r] + (q >> 2));
+                }
+            } else {
                 L->A.upload(H[l].A, f32, s);
+            }
             L->P.upload(H[l].P, f32, s);
             L->R.upload(H[l].R, f32, s);
         }

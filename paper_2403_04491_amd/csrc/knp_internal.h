@@ -168,7 +168,8 @@ struct DevCsr {
 // per vertex pair with the four field values side by side: block row v is region
 // vertex v (region i first, then region e), its entries index region-local
 // vertices, and vals[4k + f] is the field-f value of entry k.  Its vectors are in
-// the solver's order, (region r, field f, local vertex j) at off_r + 4 j + f.
+// the solver's order, (region r, field f, local vertex j) at off_r + 4 j + f, except
+// the residual handed to the restriction, which is field-major (off_r + f N_r + j).
 constexpr int FB_CAP = 1024;        // vertex-pair entries per row block (4 products each)
 struct FieldBlockView {
     int64_t nv = 0, nnz = 0, nblk = 0;   // block rows, entries, row blocks
@@ -316,7 +317,9 @@ void cheb_step(const CsrView &A, const T *val, const T *x_in, const T *b, T *d, 
 // x += P xc
 template <typename T>
 void prolong_add(const CsrView &P, const T *val, const T *xc, T *x, hipStream_t s);
-// the same residual and Chebyshev step on the field-block layout of level 0
+// the same residual and Chebyshev step on the field-block layout of level 0; the
+// residual y is written field-major (off_r + f N_r + j), the order of the
+// restriction's columns on level 0
 template <typename T>
 void fb_residual(const FieldBlockView &A, const T *val, const T *x, const T *b, T *y, hipStream_t s);
 template <typename T>

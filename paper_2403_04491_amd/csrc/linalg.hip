@@ -210,7 +210,8 @@ __global__ void __launch_bounds__(TPB) k_prolong_add(const int64_t *__restrict__
 // side by side and the four x values of that vertex as one vector gather, and
 // stages the four products in LDS.  Phase 2: four threads per block row, one per
 // field, sum the row's products in entry order (the scalar stream's order, so the
-// sums match it bit for bit) and hand them to the epilogue.
+// sums match it bit for bit) and hand them to the epilogue with the DOF in the
+// solver's order (off_r + 4 j + f) and in field-major order (off_r + f N_r + j).
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 
 template <typename T>
@@ -261,16 +262,32 @@ __device__ inline void stream_field_blocks(const FieldBlockView &fb, const T *__
         const int a = int(fb.rowptr[row] - k0), b = int(fb.rowptr[row + 1] - k0);
         A sum = A(0);
         for (int k = a; k < b; ++k) sum += prod[f][k];
-        epi(int32_t(base + 4 * (row - vfirst) + f), sum);
+        const int64_t j = row - vfirst;
+        epi(int32_t(base + 4 * j + f), int32_t(base + f * Nr + j), sum);
     }
 }
+
+// the residual goes out field-major: its only reader is the restriction, each of
+// whose rows lies in one field
+template <typename T, typename A>
+struct FbResidualFM {
+    const T *b;
+    T *y;
+    __device__ void operator()(int32_t i, int32_t ifm, A s) const { y[ifm] = T(A(b[i]) - s); }
+};
+
+template <typename T, typename A>
+struct FbCheb {
+    EpiCheb<T, A> e;
+    __device__ void operator()(int32_t i, int32_t, A s) const { e(i, s); }
+};
 
 template <typename T>
 __global__ void __launch_bounds__(TPB) k_fb_residual(FieldBlockView fb, const T *__restrict__ val,
                                                      const T *__restrict__ x, const T *__restrict__ b,
                                                      T *__restrict__ y) {
     using A = typename Acc<T>::type;
-    EpiResidual<T, A> e{b, y};
+    FbResidualFM<T, A> e{b, y};
     stream_field_blocks<T, A>(fb, val, x, e);
 }
 
@@ -279,7 +296,7 @@ __global__ void __launch_bounds__(TPB) k_fb_cheb(FieldBlockView fb, const T *__r
                                                  const T *__restrict__ xin, const T *__restrict__ b,
                                                  T *__restrict__ d, T *__restrict__ xout, double c1, double c2) {
     using A = typename Acc<T>::type;
-    EpiCheb<T, A> e{xin, b, d, xout, A(c1), A(c2), c1 != 0.0};
+    FbCheb<T, A> e{EpiCheb<T, A>{xin, b, d, xout, A(c1), A(c2), c1 != 0.0}};
     stream_field_blocks<T, A>(fb, val, xin, e);
 }
 
