@@ -85,8 +85,7 @@ def run_precision(solver, u0, g0, precision, warmup, steps, log, first_restart, 
 # that define the kernels and the data layout are the ones the counters were taken on.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_lattice132.json")
 TRAFFIC_SOURCES = ["paper_2403_04491_amd/csrc/linalg.hip", "paper_2403_04491_amd/csrc/knp_internal.h",
-                   "paper_2403_04491_amd/csrc/api.cpp", "paper_2403_04491_amd/csrc/amg.cpp",
-                   "paper_2403_04491_amd/csrc/solver.cpp"]
+                   "paper_2403_04491_amd/csrc/api.cpp", "paper_2403_04491_amd/csrc/amg.cpp"]
 
 
 def source_digests():

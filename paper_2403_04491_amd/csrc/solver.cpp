@@ -93,12 +93,16 @@ knp_status krylov_solve(knp_ctx *c, bool transpose, const double *b, double *x, 
     int stall = 0;
     bool cycle_est_converged = false;
     double window_beta = 0.0;
+    double true_rel = 1.0;   // recomputed residual of the current iterate
+    // every exit below happens right after the residual of the current iterate is
+    // recomputed, so that residual is the one reported
     while (true) {
         apply_operator(c, transpose, yh, w);
         launch::sub(N, bh, w, w, s);
         const double beta = std::sqrt(dev_dot(c, w, w, N));
         if (!std::isfinite(beta)) throw Error{KNP_E_NUMERIC, "NaN or Inf in the residual"};
         est = beta / bnorm;
+        true_rel = est;
         if (est <= o.rtol) {
             converged = true;
             break;
@@ -191,10 +195,7 @@ knp_status krylov_solve(knp_ctx *c, bool transpose, const double *b, double *x, 
         hip_check(hipStreamSynchronize(s), "update sync");
         inf.rel_res_est = est;
     }
-    // true residual of the final iterate
-    apply_operator(c, transpose, yh, w);
-    launch::sub(N, bh, w, w, s);
-    inf.rel_res = std::sqrt(dev_dot(c, w, w, N)) / bnorm;
+    inf.rel_res = true_rel;
     if (converged) inf.rel_res_est = est;
     inf.its = its;
     inf.restarts = restarts;
