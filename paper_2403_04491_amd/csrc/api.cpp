@@ -1,6 +1,7 @@
 // The C entry points of libknp (declared in include/knp.h).  Each call checks
 // its arguments, converts every internal failure into a status code plus a
 // message, and never lets a C++ exception cross the ABI.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -202,6 +203,109 @@ void need_device(knp_ctx *c) {
     if (c->host_only) throw Error{KNP_E_STATE, "host-only context (created with device -1)"};
 }
 
+// The system matrix by vertex (VtxView): each vertex's neighbour list is the set of
+// vertices its phi row touches, and every entry of its four rows is checked against
+// the column the vertex view implies for that position.  If any row differs (or a
+// vertex's rows exceed a block, or the pairs overflow int32) the view stays off and
+// A x keeps the CSR stream.
+void build_vertex_view(knp_ctx *c, const std::vector<int32_t> &cols) {
+    c->vtx = false;
+    const int64_t N = c->hm.N, nv = N / 4, nvi = c->hm.Nr[0];
+    if (nv == 0 || 4 * nv != N) return;
+    const std::vector<int64_t> &rp = c->rowptr_s;
+    std::vector<int64_t> cnt(nv + 1, 0);
+    std::vector<char> bad(nv, 0);
+#pragma omp parallel for schedule(static)
+    for (int64_t v = 0; v < nv; ++v) {
+        if (rp[4 * v + 4] - rp[4 * v] > VTX_CAP) {
+            bad[v] = 1;
+            continue;
+        }
+        std::vector<int32_t> w;
+        for (int64_t k = rp[4 * v + 3]; k < rp[4 * v + 4]; ++k) w.push_back(cols[k] >> 2);
+        std::sort(w.begin(), w.end());
+        cnt[v + 1] = std::unique(w.begin(), w.end()) - w.begin();
+    }
+    for (int64_t v = 0; v < nv; ++v) cnt[v + 1] += cnt[v];
+    if (cnt[nv] >= (int64_t(1) << 31)) return;
+    std::vector<int32_t> nbr(std::max<int64_t>(1, cnt[nv]));
+#pragma omp parallel for schedule(static)
+    for (int64_t v = 0; v < nv; ++v) {
+        if (bad[v]) continue;
+        const int64_t pb = cnt[v], npv = cnt[v + 1] - cnt[v];
+        std::vector<int32_t> w;
+        for (int64_t k = rp[4 * v + 3]; k < rp[4 * v + 4]; ++k) w.push_back(cols[k] >> 2);
+        std::sort(w.begin(), w.end());
+        w.erase(std::unique(w.begin(), w.end()), w.end());
+        const bool ext = v >= nvi;
+        int64_t m = 0;
+        for (int32_t u : w) m += (u >= nvi) == ext;
+        const int64_t p = npv - m;
+        const int64_t sb = ext ? p : 0, cb = ext ? 0 : m;
+        // same-region neighbours and partners each form one contiguous run
+        for (int64_t q = 0; q < npv; ++q) {
+            nbr[pb + q] = w[q];
+            if (((w[q] >= nvi) == ext) != (q >= sb && q < sb + m)) bad[v] = 1;
+        }
+        if (10 * m + 4 * p != rp[4 * v + 4] - rp[4 * v]) bad[v] = 1;
+        for (int f = 0; f < 4 && !bad[v]; ++f) {
+            const int64_t a = rp[4 * v + f], len = rp[4 * v + f + 1] - a;
+            if (len != (f < 3 ? 2 * m + p : 4 * m + p)) {
+                bad[v] = 1;
+                break;
+            }
+            int64_t e = 0;
+            auto seg = [&](int64_t base, int64_t n, int g) {
+                for (int64_t i = 0; i < n; ++i, ++e)
+                    if (cols[a + e] != 4 * w[base + i] + g) bad[v] = 1;
+            };
+            if (ext) seg(cb, p, 3);
+            if (f < 3) {
+                seg(sb, m, f);
+                seg(sb, m, 3);
+            } else {
+                for (int g = 0; g < 4; ++g) seg(sb, m, g);
+            }
+            if (!ext) seg(cb, p, 3);
+        }
+    }
+    for (int64_t v = 0; v < nv; ++v)
+        if (bad[v]) return;
+    std::vector<int64_t> vptr(nv + 1);
+    for (int64_t v = 0; v <= nv; ++v) vptr[v] = rp[4 * v];
+    std::vector<int32_t> nptr(nv + 1);
+    for (int64_t v = 0; v <= nv; ++v) nptr[v] = int32_t(cnt[v]);
+    std::vector<int32_t> blk{0};
+    for (int64_t v = 0; v < nv;) {
+        int64_t e = v;
+        while (e < nv && vptr[e + 1] - vptr[v] <= VTX_CAP && e - v < VTX_VMAX) ++e;
+        blk.push_back(int32_t(e));   // e > v: every vertex fits a block (checked above)
+        v = e;
+    }
+    hipStream_t s = c->stream;
+    c->d_vptr.alloc(vptr.size());
+    c->d_vptr.upload(vptr, s);
+    c->d_nptr.alloc(nptr.size());
+    c->d_nptr.upload(nptr, s);
+    c->d_nbr.alloc(nbr.size());
+    c->d_nbr.upload(nbr, s);
+    c->d_vblk.alloc(blk.size());
+    c->d_vblk.upload(blk, s);
+    std::vector<int64_t> kblk(blk.size());
+    std::vector<int32_t> pblk(blk.size());
+    for (size_t b = 0; b < blk.size(); ++b) {
+        kblk[b] = vptr[blk[b]];
+        pblk[b] = nptr[blk[b]];
+    }
+    c->d_kblk.alloc(kblk.size());
+    c->d_kblk.upload(kblk, s);
+    c->d_pblk.alloc(pblk.size());
+    c->d_pblk.upload(pblk, s);
+    c->npairs = cnt[nv];
+    c->nvblk = int64_t(blk.size()) - 1;
+    c->vtx = true;
+}
+
 }  // namespace
 
 extern "C" {
@@ -368,6 +472,7 @@ knp_status knp_mesh_upload(knp_ctx *c, int dim, int64_t n_vert, const double *xy
                 c->nblkA = int64_t(b.size()) - 1;
                 c->d_blkA.alloc(b.size());
                 c->d_blkA.upload(b, s);
+                build_vertex_view(c, cols);
                 hip_check(hipStreamSynchronize(s), "system upload");
             }
             c->d_vals.alloc(h.nnz);

@@ -50,6 +50,11 @@ struct knp_ctx {
     std::vector<int32_t> int2ext, ext2int;
     knp::DArray<int32_t> d_blkA;
     int64_t nblkA = 0;
+    // A by vertex (knp::VtxView); used for A x when every row fits the pattern
+    bool vtx = false;
+    int64_t npairs = 0, nvblk = 0;
+    knp::DArray<int64_t> d_vptr, d_kblk;
+    knp::DArray<int32_t> d_nptr, d_nbr, d_vblk, d_pblk;
     knp::DArray<int32_t> d_flag;
     double dt_static = -1.0;
     double dt_first = -1.0;
@@ -88,6 +93,25 @@ struct knp_ctx {
         v.col = d_colidx.p;
         v.blk = d_blkA.p;
         return v;
+    }
+    knp::VtxView viewV() const {
+        knp::VtxView v;
+        v.nv = hm.N / 4;
+        v.nv_i = hm.Nr[0];
+        v.nblk = nvblk;
+        v.vptr = d_vptr.p;
+        v.nptr = d_nptr.p;
+        v.nbr = d_nbr.p;
+        v.blk = d_vblk.p;
+        v.kblk = d_kblk.p;
+        v.pblk = d_pblk.p;
+        return v;
+    }
+    // algorithmic bytes of one A x through the vertex view, x of xbytes per entry
+    double vtx_bytes(double xbytes) const {
+        const double nv = double(hm.N / 4);
+        return 8.0 * double(hm.nnz) + 4.0 * double(npairs) + 12.0 * (nv + 1.0) + (xbytes + 8.0) * double(hm.N) +
+               16.0 * double(nvblk + 1);
     }
     knp::CsrView viewT() const {
         knp::CsrView v;

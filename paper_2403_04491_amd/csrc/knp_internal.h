@@ -133,6 +133,32 @@ struct CsrView {
     const int32_t *blk = nullptr;
 };
 
+// Device view of the system matrix by vertex.  Storage rows 4v..4v+3 are the four
+// fields of vertex v (region i's vertices 0..nv_i-1 first, then region e's), and
+// their columns follow from the vertex's neighbour list nbr[nptr[v]..nptr[v+1]),
+// ascending: the m neighbours in its own region (itself among them) and the p
+// membrane partners in the other region, which therefore come first for a region-e
+// vertex and last for a region-i one.  In its entry order, a concentration row (f <
+// 3) holds field f and then phi of the m neighbours, a phi row the fields 0, 1, 2,
+// 3 of the m neighbours, and either row phi of the p partners before (region e) or
+// after (region i) those.  The values stay in the CSR storage: vptr[v] is the
+// first entry of row 4v, and m follows from the entry count 10 m + 4 p.  Block b
+// owns vertices blk[b]..blk[b+1]-1 (at most VTX_VMAX), whose entries (at most
+// VTX_CAP) start at kblk[b] = vptr[blk[b]] and whose pairs start at pblk[b] =
+// nptr[blk[b]].
+struct VtxView {
+    int64_t nv = 0, nv_i = 0, nblk = 0;
+    const int64_t *vptr = nullptr;
+    const int32_t *nptr = nullptr;
+    const int32_t *nbr = nullptr;
+    const int32_t *blk = nullptr;
+    const int64_t *kblk = nullptr;
+    const int32_t *pblk = nullptr;
+};
+constexpr int VTX_CAP = 1536;
+constexpr int VTX_VMAX = 32;
+constexpr int VTX_RUNS = 14;   // runs per vertex: 3 per concentration row, 5 for phi
+
 constexpr int STREAM_CAP = 2048;   // entries per row block (8 per thread of 256)
 // Zeroed entries after the column indices and values of every level matrix: the
 // FP32 stream reads 4 consecutive entries per lane from a 4-aligned start, up to
@@ -307,6 +333,9 @@ void gather(int64_t n, const double *src, const int64_t *map, double *dst, hipSt
 // sparse and dense linear algebra (block-streamed CSR)
 template <typename TM, typename TX, typename TY>
 void spmv(const CsrView &A, const TM *val, const TX *x, TY *y, hipStream_t s);
+// y = A x for the system matrix by vertex (FP64 values and result)
+template <typename TX>
+void spmv_vtx(const VtxView &A, const double *val, const TX *x, double *y, hipStream_t s);
 // y = b - A x
 template <typename T>
 void residual(const CsrView &A, const T *val, const T *x, const T *b, T *y, hipStream_t s);

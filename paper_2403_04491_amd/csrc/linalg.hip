@@ -300,6 +300,107 @@ __global__ void __launch_bounds__(TPB) k_fb_cheb(FieldBlockView fb, const T *__r
     stream_field_blocks<T, A>(fb, val, xin, e);
 }
 
+// ---------------------------------------------------------------- A by vertex
+// The system matrix streamed by vertex (VtxView).  Phase 1: the block's values go
+// to LDS with unit-stride non-temporal loads (8 per thread), and each neighbour's
+// four x values are gathered once, as one 16- or 32-byte load, into LDS (a pair
+// owns at least 4 entries, so a block has at most VTX_CAP / 4 pairs), beside the
+// entry and pair starts of the block's vertices.  Phase 2: a row's entries are
+// runs of consecutive pairs against one field (a concentration row: its own field,
+// phi, the partners; the phi row: fields 0-3, the partners); one thread sums each
+// run in entry order.  Phase 3: each row adds its run sums in order.  The result
+// is deterministic (fixed order, no atomics); the association differs from the
+// CSR stream's single chain, so the two agree to rounding.
+template <typename TX>
+__global__ void __launch_bounds__(TPB) k_spmv_vtx(VtxView A, const double *__restrict__ val,
+                                                  const TX *__restrict__ x, double *__restrict__ y) {
+    static_assert(VTX_CAP % TPB == 0, "whole entries per thread");
+    constexpr int PER = VTX_CAP / TPB;
+    constexpr int PPER = (VTX_CAP / 4 + TPB - 1) / TPB;
+    __shared__ double vs[VTX_CAP];
+    __shared__ TX xs[VTX_CAP];
+    const int lb = int(blockIdx.x);
+    if (lb >= A.nblk) return;
+    const int32_t v0 = A.blk[lb], v1 = A.blk[lb + 1];
+    const int64_t k0 = A.kblk[lb];
+    const int n = int(A.kblk[lb + 1] - k0);
+    const int32_t p0 = A.pblk[lb];
+    const int np = A.pblk[lb + 1] - p0;
+    __shared__ int vo[VTX_VMAX + 1], vp[VTX_VMAX + 1];   // entry and pair starts of the block's vertices
+    __shared__ double part[VTX_RUNS * VTX_VMAX];        // run sums
+    const int nvb = v1 - v0;
+    for (int t = int(threadIdx.x); t <= nvb; t += TPB) {
+        vo[t] = int(A.vptr[v0 + t] - k0);
+        vp[t] = A.nptr[v0 + t] - p0;
+    }
+    double v[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int i = threadIdx.x + u * TPB;
+        if (i < n) v[u] = __builtin_nontemporal_load(val + k0 + i);
+    }
+    TX xv[PPER][4];
+#pragma unroll
+    for (int u = 0; u < PPER; ++u) {
+        const int q = threadIdx.x + u * TPB;
+        if (q < np) load4<TX>(x + 4 * int64_t(__builtin_nontemporal_load(A.nbr + p0 + q)), xv[u], false);
+    }
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int i = threadIdx.x + u * TPB;
+        if (i < n) vs[i] = v[u];
+    }
+#pragma unroll
+    for (int u = 0; u < PPER; ++u) {
+        const int q = threadIdx.x + u * TPB;
+        if (q < np)
+#pragma unroll
+            for (int g = 0; g < 4; ++g) xs[4 * q + g] = xv[u][g];
+    }
+    __syncthreads();
+    // phase 2: one thread per run (14 per vertex: rows 0-2 have 3, row 3 has 5)
+    for (int r = int(threadIdx.x); r < VTX_RUNS * nvb; r += TPB) {
+        const int t = r / VTX_RUNS, k = r - t * VTX_RUNS;
+        const int f = k < 9 ? k / 3 : 3, j = k < 9 ? k - 3 * f : k - 9;   // row, run within the row
+        const int o0 = vo[t], len = vo[t + 1] - o0;
+        const int pb = vp[t], npv = vp[t + 1] - pb;
+        const int m = (len - 4 * npv) / 6;
+        const int p = npv - m;
+        const bool cf = v0 + t >= A.nv_i;   // partners first (region e)
+        const int nsame = f < 3 ? 2 : 4;   // same-region runs in this row
+        int o = o0 + (f < 3 ? f : 3) * (2 * m + p), base, cnt, g;
+        const int js = cf ? j - 1 : j;      // index among the same-region runs
+        if (cf ? j == 0 : j == nsame) {
+            o += cf ? 0 : nsame * m;
+            base = pb + (cf ? 0 : m);
+            cnt = p;
+            g = 3;
+        } else {
+            o += (cf ? p : 0) + js * m;
+            base = pb + (cf ? p : 0);
+            cnt = m;
+            g = f < 3 ? (js == 0 ? f : 3) : js;
+        }
+        double sum = 0.0;
+#pragma unroll 8
+        for (int e = 0; e < cnt; ++e) sum += vs[o + e] * double(xs[4 * (base + e) + g]);
+        part[r] = sum;
+    }
+    __syncthreads();
+    // phase 3: each row adds its runs in order
+    for (int r = int(threadIdx.x); r < 4 * nvb; r += TPB) {
+        const int t = r >> 2, f = r & 3;
+        const double *q = part + t * VTX_RUNS + (f < 3 ? 3 * f : 9);
+        double sum = q[0] + q[1];
+        sum += q[2];
+        if (f == 3) {
+            sum += q[3];
+            sum += q[4];
+        }
+        y[4 * int64_t(v0 + t) + f] = sum;
+    }
+}
+
 template <typename TA, typename TB>
 __global__ void k_convert(int64_t n, const TA *__restrict__ a, TB *__restrict__ b) {
     for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
@@ -451,6 +552,12 @@ void spmv(const CsrView &A, const TM *val, const TX *x, TY *y, hipStream_t s) {
                        int(A.nblk), y);
 }
 
+template <typename TX>
+void spmv_vtx(const VtxView &A, const double *val, const TX *x, double *y, hipStream_t s) {
+    if (A.nblk == 0) return;
+    hipLaunchKernelGGL((k_spmv_vtx<TX>), dim3(block_grid(A.nblk)), dim3(TPB), 0, s, A, val, x, y);
+}
+
 template <typename T>
 void residual(const CsrView &A, const T *val, const T *x, const T *b, T *y, hipStream_t s) {
     if (A.nblk == 0) return;
@@ -553,6 +660,8 @@ void sub(int64_t n, const double *a, const double *b, double *y, hipStream_t s) 
 }
 
 // explicit instantiations
+template void spmv_vtx<double>(const VtxView &, const double *, const double *, double *, hipStream_t);
+template void spmv_vtx<float>(const VtxView &, const double *, const float *, double *, hipStream_t);
 template void spmv<double, double, double>(const CsrView &, const double *, const double *, double *, hipStream_t);
 template void spmv<double, float, double>(const CsrView &, const double *, const float *, double *, hipStream_t);
 template void spmv<float, float, float>(const CsrView &, const float *, const float *, float *, hipStream_t);

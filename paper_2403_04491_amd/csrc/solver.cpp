@@ -50,10 +50,15 @@ void ensure_workspace(knp_ctx *c, int m, bool z32) {
 void apply_operator(knp_ctx *c, bool transpose, const double *x, double *y) {
     const int64_t N = c->hm.N;
     hipEvent_t t0 = c->tm.begin(KNP_TIMER_SPMV_A, c->stream);
-    if (transpose)
+    if (transpose) {
         launch::spmv<double, double, double>(c->viewT(), c->d_valsT.p, x, y, c->stream);
-    else
+    } else if (c->vtx) {
+        launch::spmv_vtx<double>(c->viewV(), c->d_vals.p, x, y, c->stream);
+        c->tm.end(KNP_TIMER_SPMV_A, t0, c->vtx_bytes(8.0), c->stream);
+        return;
+    } else {
         launch::spmv<double, double, double>(c->viewA(), c->d_vals.p, x, y, c->stream);
+    }
     c->tm.end(KNP_TIMER_SPMV_A, t0, 12.0 * double(c->hm.nnz) + 32.0 * double(N) + 8.0, c->stream);
 }
 
@@ -128,9 +133,14 @@ knp_status krylov_solve(knp_ctx *c, bool transpose, const double *b, double *x, 
                     float *zj = c->Z32.p + size_t(j) * N;
                     amg_vcycle(c->amg, vj, zj, s, &c->tm);
                     hipEvent_t t0 = c->tm.begin(KNP_TIMER_SPMV_A, s);
-                    launch::spmv<double, float, double>(transpose ? c->viewT() : c->viewA(),
-                                                        transpose ? c->d_valsT.p : c->d_vals.p, zj, wj, s);
-                    c->tm.end(KNP_TIMER_SPMV_A, t0, 12.0 * double(c->hm.nnz) + 28.0 * double(N) + 8.0, s);
+                    if (!transpose && c->vtx) {
+                        launch::spmv_vtx<float>(c->viewV(), c->d_vals.p, zj, wj, s);
+                        c->tm.end(KNP_TIMER_SPMV_A, t0, c->vtx_bytes(4.0), s);
+                    } else {
+                        launch::spmv<double, float, double>(transpose ? c->viewT() : c->viewA(),
+                                                            transpose ? c->d_valsT.p : c->d_vals.p, zj, wj, s);
+                        c->tm.end(KNP_TIMER_SPMV_A, t0, 12.0 * double(c->hm.nnz) + 28.0 * double(N) + 8.0, s);
+                    }
                 } else {
                     double *zj = c->Z64.p + size_t(j) * N;
                     amg_vcycle(c->amg, vj, zj, s, &c->tm);

@@ -283,10 +283,13 @@ def test_error_paths():
 
 
 def test_deterministic_rerun():
+    # the first step from the noisy initial state takes several hundred iterations
+    # at rtol 1e-10, a count that moves with the rounding of the operator; the test
+    # is about bitwise repetition, so the cap is generous
     case = model_a_case(3, 8, "hh", 5e-5, 2, cfg_id=2)
     outs = []
     for _ in range(2):
-        s = KnpSolver(case, solve=solve_opts(rtol=1e-10, restart=100, max_it=500))
+        s = KnpSolver(case, solve=solve_opts(rtol=1e-10, restart=100, max_it=2000))
         s.step()
         s.step()
         outs.append(s.u.cpu().numpy())
