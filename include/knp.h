@@ -88,6 +88,9 @@ typedef struct {
     double cheb_ratio;      /* smoothing interval [lmax/cheb_ratio, lmax] (> 1)   */
     int32_t coarse_max;     /* coarsen until at most this many unknowns           */
     int32_t max_levels;
+    double coarse_drop;     /* drop coarse-operator couplings with |a_ij| <        */
+                            /* coarse_drop * sqrt(a_ii a_jj), lumped into a_ii     */
+                            /* near-nullspace weighted (0: exact Galerkin; >= 0)   */
 } knp_amg_opts;
 
 typedef struct {
@@ -165,7 +168,7 @@ knp_status knp_assemble_step(knp_ctx *ctx, double t_n, double dt, const double *
 /* Build the algebraic-multigrid hierarchy of P_0 (eq. ``P_prec``), frozen for all
  * steps (same section).  Must follow the first knp_assemble_step (else
  * KNP_E_STATE).  opts NULL = defaults (FP64, strength 0.25, Chebyshev degree 3 on
- * [lmax/2.5, lmax], coarse_max 2000, max_levels 20). */
+ * [lmax/2.5, lmax], coarse_max 2000, max_levels 20, coarse_drop 0.01). */
 knp_status knp_amg_setup(knp_ctx *ctx, const knp_amg_opts *opts);
 
 /* Shape of the hierarchy built by knp_amg_setup: number of levels (<= 32) and,
@@ -220,7 +223,7 @@ knp_status knp_get_values(knp_ctx *ctx, double *vals);
  * bytes the kernel must move at least once: matrix values and indices, row
  * pointers, each vector read or written once). */
 enum { KNP_TIMER_SPMV_A = 0,        /* y = (S A S) x, Krylov operator          */
-       KNP_TIMER_CHEB_L0 = 1,       /* Chebyshev step on the finest AMG level  */
+       KNP_TIMER_CHEB_L0 = 1,       /* Chebyshev steps on the finest AMG level that apply the operator */
        KNP_TIMER_RESID_L0 = 2,      /* residual on the finest AMG level        */
        KNP_TIMER_VCYCLE = 3,        /* one whole V-cycle                        */
        KNP_TIMER_ASSEMBLY = 4,      /* knp_assemble_step device work            */

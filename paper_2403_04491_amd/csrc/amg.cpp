@@ -7,8 +7,9 @@
 // negative couplings relative to the row's largest, greedy three-phase
 // aggregation, tentative prolongator from the near-nullspace vector (the
 // constant in unscaled variables), one damped-Jacobi smoothing step on the
-// strength-filtered operator, Galerkin product R A P with R = P^T, and a
-// symmetric rescaling of the coarse operator to unit diagonal (absorbed into P
+// strength-filtered operator, Galerkin product R A P with R = P^T, weak couplings
+// of the product dropped (lumped into the diagonal, near-nullspace weighted), and
+// a symmetric rescaling of the coarse operator to unit diagonal (absorbed into P
 // and R).  Aggregates never cross the blocks of P_0 because P_0 has no
 // couplings between them.  The coarsest level is solved with one dense FP64
 // inverse per connected component.
@@ -52,6 +53,53 @@ Csr transpose(const Csr &A) {
 
 // C = A B, rows computed independently (deterministic: accumulation follows the
 // order of A's row and B's rows); columns sorted per row.
+// Drops the couplings of a coarse operator with |a_ij| < tol sqrt(a_ii a_jj) and
+// adds a_ij b_j / b_i to a_ii (b the coarse near-nullspace vector), so that A b is
+// unchanged; the criterion is symmetric, so the result stays symmetric.  If that
+// would take any diagonal below half its value, the operator is left exact.
+void sparsify(Csr &A, const std::vector<double> &b, double tol) {
+    const int64_t n = A.nrows;
+    std::vector<double> dg(n, 0.0), lump(n, 0.0);
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t k = A.rowptr[i]; k < A.rowptr[i + 1]; ++k)
+            if (A.col[k] == i) dg[i] = A.val[k];
+    std::vector<char> keep(A.nnz());
+    std::vector<int64_t> cnt(n + 1, 0);
+    bool ok = true;
+#pragma omp parallel for schedule(static) reduction(&& : ok)
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t c = 0;
+        for (int64_t k = A.rowptr[i]; k < A.rowptr[i + 1]; ++k) {
+            const int32_t j = A.col[k];
+            const bool kp = j == i || std::fabs(A.val[k]) >= tol * std::sqrt(std::fabs(dg[i] * dg[j]));
+            keep[k] = kp;
+            c += kp;
+            if (!kp && b[i] != 0.0) lump[i] += A.val[k] * b[j] / b[i];
+        }
+        cnt[i + 1] = c;
+        ok = ok && dg[i] + lump[i] >= 0.5 * dg[i];
+    }
+    if (!ok) return;
+    for (int64_t i = 0; i < n; ++i) cnt[i + 1] += cnt[i];
+    Csr K;
+    K.nrows = A.nrows;
+    K.ncols = A.ncols;
+    K.rowptr = cnt;
+    K.col.resize(cnt[n]);
+    K.val.resize(cnt[n]);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t o = K.rowptr[i];
+        for (int64_t k = A.rowptr[i]; k < A.rowptr[i + 1]; ++k)
+            if (keep[k]) {
+                K.col[o] = A.col[k];
+                K.val[o] = A.val[k] + (A.col[k] == i ? lump[i] : 0.0);
+                ++o;
+            }
+    }
+    A = std::move(K);
+}
+
 Csr spgemm(const Csr &A, const Csr &B) {
     Csr C;
     C.nrows = A.nrows;
@@ -518,6 +566,7 @@ void amg_build(Amg &amg, const HostMesh &m, const std::vector<double> &p0_vals, 
             Csr AP = spgemm(L.A, P);
             Ac = spgemm(R, AP);
         }
+        if (o.coarse_drop > 0.0) sparsify(Ac, bn, o.coarse_drop);
         // unit diagonal on the coarse level, absorbed into P and R
         std::vector<double> dc(nc, 1.0);
         for (int64_t c = 0; c < nc; ++c)
@@ -734,16 +783,16 @@ T *vcycle_level(Amg &amg, size_t l, const T *b, hipStream_t s, Timers *tm, T *ou
     const double mat = fbl ? double(L->fb.nnz) * (4.0 * vb + 4.0) + 8.0 * double(L->fb.nv + 1)
                            : double(L->A.nnz) * (vb + 4.0) + 8.0 * double(n + 1);
     Timers *t0 = (l == 0) ? tm : nullptr;
+    // the finest level's timer class holds the steps that apply the operator (the
+    // first step from x = 0 is a plain vector update)
     auto cheb = [&](const T *xin, T *xout, double c1, double c2) {
-        hipEvent_t e = t0 ? t0->begin(KNP_TIMER_CHEB_L0, s) : nullptr;
+        Timers *tc = xin ? t0 : nullptr;
+        hipEvent_t e = tc ? tc->begin(KNP_TIMER_CHEB_L0, s) : nullptr;
         if (fbl)
             launch::fb_cheb_step<T>(L->fb.view(), av, xin, b, d, xout, c1, c2, s);
         else
             launch::cheb_step<T>(L->A.view(), av, xin, b, d, xout, c1, c2, s);
-        if (t0) {
-            const double bytes = xin ? mat + vb * double(n) * (c1 != 0.0 ? 5.0 : 4.0) : 3.0 * vb * double(n);
-            t0->end(KNP_TIMER_CHEB_L0, e, bytes, s);
-        }
+        if (tc) tc->end(KNP_TIMER_CHEB_L0, e, mat + vb * double(n) * (c1 != 0.0 ? 5.0 : 4.0), s);
     };
     // pre-smoothing from x = 0
     cheb(nullptr, x, 0.0, cc[0].second);
