@@ -4,6 +4,32 @@
 
 #include "knp_internal.h"
 
+namespace knp {
+// Pinned host buffer (hipHostMalloc): the target of the solver's small per-iteration
+// device-to-host copies, which from pageable memory cost ~0.1 ms each.
+template <typename T>
+struct PinnedArray {
+    T *p = nullptr;
+    size_t n = 0;
+    PinnedArray() = default;
+    PinnedArray(const PinnedArray &) = delete;
+    PinnedArray &operator=(const PinnedArray &) = delete;
+    ~PinnedArray() { release(); }
+    void release() {
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    void alloc(size_t count) {
+        release();
+        if (count == 0) return;
+        hip_check(hipHostMalloc(reinterpret_cast<void **>(&p), count * sizeof(T), hipHostMallocDefault),
+                  "pinned host allocation");
+        n = count;
+    }
+};
+}  // namespace knp
+
 struct knp_ctx {
     int device = -1;
     bool host_only = true;
@@ -77,6 +103,7 @@ struct knp_ctx {
     int m_alloc = -1;
     bool z32 = false;
     knp::DArray<double> V, Z64, w, bh, yh, partial, dscal;
+    knp::PinnedArray<double> hbuf;   // host side of the Hessenberg column, norms and dots
     knp::DArray<float> Z32;
     int nblk = 1;
 

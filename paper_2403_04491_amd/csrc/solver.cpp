@@ -10,6 +10,7 @@
 // FP64 and the FP32 V-cycle.  Arnoldi, the Hessenberg least-squares problem,
 // the solution update and the true-residual recomputation are FP64.
 // One device-to-host copy of the new Hessenberg column per iteration.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 
@@ -19,13 +20,17 @@ namespace knp {
 
 namespace {
 
+void ensure_pinned(knp_ctx *c, size_t count) {
+    if (c->hbuf.n < count) c->hbuf.alloc(std::max<size_t>(count, 256));
+}
+
 double dev_dot(knp_ctx *c, const double *a, const double *b, int64_t n) {
     // <a, b> via the multi-dot kernel with one vector (deterministic)
+    ensure_pinned(c, 1);
     launch::multi_dot(n, a, n, 1, b, c->dscal.p, c->partial.p, c->nblk, c->stream);
-    double h = 0.0;
-    hip_check(hipMemcpyAsync(&h, c->dscal.p, sizeof(double), hipMemcpyDeviceToHost, c->stream), "dot copy");
+    hip_check(hipMemcpyAsync(c->hbuf.p, c->dscal.p, sizeof(double), hipMemcpyDeviceToHost, c->stream), "dot copy");
     hip_check(hipStreamSynchronize(c->stream), "dot sync");
-    return h;
+    return c->hbuf.p[0];
 }
 
 void ensure_workspace(knp_ctx *c, int m, bool z32) {
@@ -41,6 +46,7 @@ void ensure_workspace(knp_ctx *c, int m, bool z32) {
         c->Z64.alloc(size_t(m) * N);
     c->dscal.release();
     c->dscal.alloc(size_t(m) + 64);
+    ensure_pinned(c, 2 * size_t(m) + 8);
     c->m_alloc = m;
     c->z32 = z32;
 }
@@ -85,7 +91,7 @@ knp_status krylov_solve(knp_ctx *c, bool transpose, const double *b, double *x, 
         if (info) *info = inf;
         return KNP_OK;
     }
-    std::vector<double> H(size_t(m + 1) * m), cs(m), sn(m), g(m + 1), hcol(m + 2), hcol2(m + 2), y(m);
+    std::vector<double> H(size_t(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
     auto Hc = [&](int i, int j) -> double & { return H[size_t(j) * (m + 1) + i]; };
     int its = 0, restarts = 0;
     double est = 1.0;
@@ -149,25 +155,24 @@ knp_status krylov_solve(knp_ctx *c, bool transpose, const double *b, double *x, 
             } else {
                 apply_operator(c, transpose, vj, wj);
             }
-            // classical Gram-Schmidt (optionally twice)
+            // classical Gram-Schmidt (optionally twice); the coefficients and the new
+            // norm (dh[m + 1]) reach the host in one copy into pinned memory, the
+            // first pass's coefficients in a copy of their own when there are two
             double *dh = c->dscal.p;
+            double *hp = c->hbuf.p;   // [0, m + 2): last pass; [m + 2, 2m + 4): first of two
             launch::multi_dot(N, V, N, j + 1, wj, dh, c->partial.p, c->nblk, s);
             launch::gs_update(N, V, N, j + 1, dh, wj, c->partial.p, c->nblk, s);
             if (o.reorth) {
-                hip_check(hipMemcpyAsync(hcol.data(), dh, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, s), "h");
+                hip_check(hipMemcpyAsync(hp + m + 2, dh, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, s), "h");
                 launch::multi_dot(N, V, N, j + 1, wj, dh, c->partial.p, c->nblk, s);
                 launch::gs_update(N, V, N, j + 1, dh, wj, c->partial.p, c->nblk, s);
-                hip_check(hipMemcpyAsync(hcol2.data(), dh, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, s), "h2");
             }
             launch::reduce_partials(1, c->nblk, c->partial.p, dh + m + 1, s);
-            if (!o.reorth)
-                hip_check(hipMemcpyAsync(hcol.data(), dh, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, s), "h");
-            double nrm2 = 0.0;
-            hip_check(hipMemcpyAsync(&nrm2, dh + m + 1, sizeof(double), hipMemcpyDeviceToHost, s), "nrm");
+            hip_check(hipMemcpyAsync(hp, dh, sizeof(double) * (m + 2), hipMemcpyDeviceToHost, s), "h");
             hip_check(hipStreamSynchronize(s), "gs sync");
-            const double hn = std::sqrt(nrm2);
+            const double hn = std::sqrt(hp[m + 1]);
             if (!std::isfinite(hn)) throw Error{KNP_E_NUMERIC, "NaN or Inf in the Arnoldi process"};
-            for (int i = 0; i <= j; ++i) Hc(i, j) = hcol[i] + (o.reorth ? hcol2[i] : 0.0);
+            for (int i = 0; i <= j; ++i) Hc(i, j) = o.reorth ? hp[m + 2 + i] + hp[i] : hp[i];
             Hc(j + 1, j) = hn;
             if (hn > 0.0) launch::scale_by_inv_norm(N, wj, dh + m + 1, wj, s);
             // Givens rotations
@@ -195,7 +200,9 @@ knp_status krylov_solve(knp_ctx *c, bool transpose, const double *b, double *x, 
             for (int k = i + 1; k < jend; ++k) t -= Hc(i, k) * y[k];
             y[i] = Hc(i, i) != 0.0 ? t / Hc(i, i) : 0.0;
         }
-        hip_check(hipMemcpyAsync(c->dscal.p, y.data(), sizeof(double) * jend, hipMemcpyHostToDevice, s), "y");
+        // (through pinned memory; the stream is synchronised before it is reused)
+        std::memcpy(c->hbuf.p, y.data(), sizeof(double) * jend);
+        hip_check(hipMemcpyAsync(c->dscal.p, c->hbuf.p, sizeof(double) * jend, hipMemcpyHostToDevice, s), "y");
         if (!use_amg)
             launch::multi_axpy<double>(N, c->V.p, N, jend, c->dscal.p, yh, s);
         else if (z32)
