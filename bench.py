@@ -382,8 +382,11 @@ def main():
     ap.add_argument("--restart", type=int, default=30)
     ap.add_argument("--cheb-degree", type=int, default=3)
     ap.add_argument("--cheb-ratio", type=float, default=2.5)
-    ap.add_argument("--strength", type=float, default=0.25)
+    ap.add_argument("--strength", type=float, default=0.6)
     ap.add_argument("--coarse-drop", type=float, default=0.01)
+    ap.add_argument("--cheb-pre-degree", type=int, default=1)
+    ap.add_argument("--coarse-pre-degree", type=int, default=0)
+    ap.add_argument("--coarse-post-degree", type=int, default=1)
     ap.add_argument("--coarse-max", type=int, default=2000)
     ap.add_argument("--kernels-only", action="store_true",
                     help="profiling mode: apply S A S and one V-cycle --reps times after setup, plus a "
@@ -435,7 +438,8 @@ def main():
     log(f"case {case.name}: {case.n_vert} vertices, {case.n_elem} tets, generated in {t_gen:.1f} s")
     t0 = time.perf_counter()
     amg_kw = dict(cheb_degree=args.cheb_degree, cheb_ratio=args.cheb_ratio, strength=args.strength,
-                  coarse_drop=args.coarse_drop,
+                  coarse_drop=args.coarse_drop, cheb_pre_degree=args.cheb_pre_degree,
+                  coarse_pre_degree=args.coarse_pre_degree, coarse_post_degree=args.coarse_post_degree,
                   coarse_max=args.coarse_max)
     solver = KnpSolver(case, solve=solve_opts(rtol=1e-6, restart=args.restart, max_it=2000))
     torch.cuda.synchronize()

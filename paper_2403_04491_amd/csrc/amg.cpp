@@ -413,6 +413,9 @@ void amg_build(Amg &amg, const HostMesh &m, const std::vector<double> &p0_vals, 
     amg.clear();
     amg.fp32 = o.precision == 1;
     amg.degree = std::max(1, o.cheb_degree);
+    amg.pre_degree = std::max(1, o.cheb_pre_degree);
+    amg.coarse_pre = std::max(0, o.coarse_pre_degree);
+    amg.coarse_post = std::max(1, o.coarse_post_degree);
     amg.ratio = o.cheb_ratio;
     // P_0 in CSR, in the solver's order (DOF off_r + 4 j + f): per region the scalar
     // pattern of the region for each field.  p0_vals and near_null come in ABI order
@@ -587,9 +590,18 @@ void amg_build(Amg &amg, const HostMesh &m, const std::vector<double> &p0_vals, 
         B.swap(Bc);
     }
 
-    // spectral bounds for Chebyshev
-    for (auto &L : H) {
+    // spectral bounds for Chebyshev: on the finest level a power estimate (x1.1,
+    // capped by Gershgorin); on the coarser levels the Gershgorin bound itself,
+    // since there 20 power steps undershot the top of the spectrum and the
+    // smoother then amplified the modes above its interval (one GMRES iteration
+    // per step more on the 132^3 lattice)
+    for (size_t l = 0; l < H.size(); ++l) {
+        HostLevel &L = H[l];
         const double g = gershgorin(L.A);
+        if (l > 0) {
+            L.lmax = g;
+            continue;
+        }
         const double pw = L.A.nrows > 1 ? 1.1 * power_lmax(L.A, 20) : g;
         L.lmax = std::min(g, std::max(pw, 1e-12));
     }
@@ -772,8 +784,12 @@ T *vcycle_level(Amg &amg, size_t l, const T *b, hipStream_t s, Timers *tm, T *ou
         }
         return x;
     }
-    std::vector<std::pair<double, double>> cc;
-    cheb_coeffs(L->lmax, amg.ratio, amg.degree, cc);
+    // smoothing degrees: the finest level pre/post, the coarser levels their own
+    const int dpre = l == 0 ? amg.pre_degree : amg.coarse_pre;
+    const int dpost = l == 0 ? amg.degree : amg.coarse_post;
+    std::vector<std::pair<double, double>> cpre, cc;
+    if (dpre > 0) cheb_coeffs(L->lmax, amg.ratio, dpre, cpre);
+    cheb_coeffs(L->lmax, amg.ratio, dpost, cc);
     const int64_t n = L->n;
     const bool fbl = l == 0;     // level 0 is P_0 in the field-block layout
     const T *av = fbl ? LV<T>::FB(L) : LV<T>::A(L);
@@ -794,26 +810,32 @@ T *vcycle_level(Amg &amg, size_t l, const T *b, hipStream_t s, Timers *tm, T *ou
             launch::cheb_step<T>(L->A.view(), av, xin, b, d, xout, c1, c2, s);
         if (tc) tc->end(KNP_TIMER_CHEB_L0, e, mat + vb * double(n) * (c1 != 0.0 ? 5.0 : 4.0), s);
     };
-    // pre-smoothing from x = 0
-    cheb(nullptr, x, 0.0, cc[0].second);
-    for (size_t k = 1; k < cc.size(); ++k) {
-        cheb(x, x2, cc[k].first, cc[k].second);
-        std::swap(x, x2);
-    }
-    // residual and restriction
-    {
+    Level *Lc = amg.levels[l + 1];
+    T *bc = LV<T>::b(Lc);
+    if (dpre > 0) {
+        // pre-smoothing from x = 0, residual, restriction
+        cheb(nullptr, x, 0.0, cpre[0].second);
+        for (size_t k = 1; k < cpre.size(); ++k) {
+            cheb(x, x2, cpre[k].first, cpre[k].second);
+            std::swap(x, x2);
+        }
         hipEvent_t e = t0 ? t0->begin(KNP_TIMER_RESID_L0, s) : nullptr;
         if (fbl)
             launch::fb_residual<T>(L->fb.view(), av, x, b, t, s);
         else
             launch::residual<T>(L->A.view(), av, x, b, t, s);
         if (t0) t0->end(KNP_TIMER_RESID_L0, e, mat + 3.0 * vb * double(n), s);
+        launch::spmv<T, T, T>(L->R.view(), LV<T>::R(L), t, bc, s);
+    } else {
+        // no pre-smoothing (a coarser level, whose restriction reads this level's
+        // order): x = 0, so the residual is b itself
+        launch::spmv<T, T, T>(L->R.view(), LV<T>::R(L), b, bc, s);
     }
-    Level *Lc = amg.levels[l + 1];
-    T *bc = LV<T>::b(Lc);
-    launch::spmv<T, T, T>(L->R.view(), LV<T>::R(L), t, bc, s);
     T *xc = vcycle_level<T>(amg, l + 1, bc, s, tm);
-    launch::prolong_add<T>(L->P.view(), LV<T>::P(L), xc, x, s);
+    if (dpre > 0)
+        launch::prolong_add<T>(L->P.view(), LV<T>::P(L), xc, x, s);
+    else
+        launch::spmv<T, T, T>(L->P.view(), LV<T>::P(L), xc, x, s);   // x = P xc
     // post-smoothing; the last step writes to `out` when given
     for (size_t k = 0; k < cc.size(); ++k) {
         T *dst = (out && k + 1 == cc.size()) ? out : x2;

@@ -237,8 +237,10 @@ struct Level {
 struct Amg {
     bool ready = false;
     bool fp32 = false;
-    int degree = 2;
-    double ratio = 10.0;
+    int degree = 3;                  // finest level: post-smoothing degree
+    int pre_degree = 2;              // finest level: pre-smoothing degree
+    int coarse_pre = 1, coarse_post = 1;   // coarser levels (pre 0: restrict b directly)
+    double ratio = 2.5;
     std::vector<Level *> levels;     // levels[0] is P_0
     // coarsest-level dense inverses, one per connected component
     int64_t n_coarse = 0;
