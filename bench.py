@@ -380,11 +380,11 @@ def main():
     ap.add_argument("--first-restart", type=int, default=200,
                     help="FGMRES restart of the untimed first step (later steps: 30)")
     ap.add_argument("--restart", type=int, default=30)
-    ap.add_argument("--cheb-degree", type=int, default=3)
+    ap.add_argument("--cheb-degree", type=int, default=5)
     ap.add_argument("--cheb-ratio", type=float, default=2.5)
     ap.add_argument("--strength", type=float, default=0.6)
     ap.add_argument("--coarse-drop", type=float, default=0.01)
-    ap.add_argument("--cheb-pre-degree", type=int, default=1)
+    ap.add_argument("--cheb-pre-degree", type=int, default=0)
     ap.add_argument("--coarse-pre-degree", type=int, default=0)
     ap.add_argument("--coarse-post-degree", type=int, default=1)
     ap.add_argument("--coarse-max", type=int, default=2000)

@@ -91,9 +91,9 @@ typedef struct {
     double coarse_drop;     /* drop coarse-operator couplings with |a_ij| <        */
                             /* coarse_drop * sqrt(a_ii a_jj), lumped into a_ii     */
                             /* near-nullspace weighted (0: exact Galerkin; >= 0)   */
-    int32_t cheb_pre_degree;     /* finest level: pre-smoothing degree (>= 1)      */
+    int32_t cheb_pre_degree;     /* finest level: pre-smoothing degree (>= 0)      */
     int32_t coarse_pre_degree;   /* coarser levels: pre-smoothing degree (>= 0;    */
-                                 /* 0 restricts the level's right-hand side)       */
+                                 /* 0, here and above: restrict the right-hand side) */
     int32_t coarse_post_degree;  /* coarser levels: post-smoothing degree (>= 1)   */
 } knp_amg_opts;
 
@@ -172,7 +172,7 @@ knp_status knp_assemble_step(knp_ctx *ctx, double t_n, double dt, const double *
 /* Build the algebraic-multigrid hierarchy of P_0 (eq. ``P_prec``), frozen for all
  * steps (same section).  Must follow the first knp_assemble_step (else
  * KNP_E_STATE).  opts NULL = defaults (FP64, strength 0.6, Chebyshev smoothing on
- * [lmax/2.5, lmax] of degree 1 before and 3 after the coarse correction on the
+ * [lmax/2.5, lmax] of degree 0 before and 5 after the coarse correction on the
  * finest level and 0 and 1 on the coarser levels, coarse_max 2000, max_levels 20,
  * coarse_drop 0.01). */
 knp_status knp_amg_setup(knp_ctx *ctx, const knp_amg_opts *opts);

@@ -413,7 +413,7 @@ void amg_build(Amg &amg, const HostMesh &m, const std::vector<double> &p0_vals, 
     amg.clear();
     amg.fp32 = o.precision == 1;
     amg.degree = std::max(1, o.cheb_degree);
-    amg.pre_degree = std::max(1, o.cheb_pre_degree);
+    amg.pre_degree = std::max(0, o.cheb_pre_degree);
     amg.coarse_pre = std::max(0, o.coarse_pre_degree);
     amg.coarse_post = std::max(1, o.coarse_post_degree);
     amg.ratio = o.cheb_ratio;
@@ -827,9 +827,14 @@ T *vcycle_level(Amg &amg, size_t l, const T *b, hipStream_t s, Timers *tm, T *ou
         if (t0) t0->end(KNP_TIMER_RESID_L0, e, mat + 3.0 * vb * double(n), s);
         launch::spmv<T, T, T>(L->R.view(), LV<T>::R(L), t, bc, s);
     } else {
-        // no pre-smoothing (a coarser level, whose restriction reads this level's
-        // order): x = 0, so the residual is b itself
-        launch::spmv<T, T, T>(L->R.view(), LV<T>::R(L), b, bc, s);
+        // no pre-smoothing: x = 0, so the residual is b itself (on level 0 taken to
+        // field-major order, the restriction's column order there)
+        if (fbl) {
+            launch::to_field_major<T>(L->fb.view(), b, t, s);
+            launch::spmv<T, T, T>(L->R.view(), LV<T>::R(L), t, bc, s);
+        } else {
+            launch::spmv<T, T, T>(L->R.view(), LV<T>::R(L), b, bc, s);
+        }
     }
     T *xc = vcycle_level<T>(amg, l + 1, bc, s, tm);
     if (dpre > 0)

@@ -356,6 +356,9 @@ void fb_residual(const FieldBlockView &A, const T *val, const T *x, const T *b, 
 template <typename T>
 void fb_cheb_step(const FieldBlockView &A, const T *val, const T *x_in, const T *b, T *d, T *x_out, double c1,
                   double c2, hipStream_t s);
+// a level-0 vector into field-major order (the restriction's column order)
+template <typename T>
+void to_field_major(const FieldBlockView &A, const T *src, T *dst, hipStream_t s);
 template <typename TA, typename TB>
 void convert(int64_t n, const TA *a, TB *b, hipStream_t s);
 void coarse_solve(int64_t n, const int32_t *comp, const int32_t *cloc, const int32_t *cmem, const int64_t *cstart,

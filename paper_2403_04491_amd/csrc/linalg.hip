@@ -401,6 +401,18 @@ __global__ void __launch_bounds__(TPB) k_spmv_vtx(VtxView A, const double *__res
     }
 }
 
+// level-0 vector from the solver's order (off_r + 4 j + f) to field-major order
+// (off_r + f N_r + j), the order of the restriction's columns on level 0
+template <typename T>
+__global__ void k_to_field_major(int64_t Ni, int64_t Ne, const T *__restrict__ src, T *__restrict__ dst) {
+    const int64_t n = 4 * (Ni + Ne);
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
+        const bool ext = i >= 4 * Ni;
+        const int64_t base = ext ? 4 * Ni : 0, li = i - base;
+        dst[base + (li & 3) * (ext ? Ne : Ni) + (li >> 2)] = src[i];
+    }
+}
+
 template <typename TA, typename TB>
 __global__ void k_convert(int64_t n, const TA *__restrict__ a, TB *__restrict__ b) {
     for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
@@ -552,6 +564,13 @@ void spmv(const CsrView &A, const TM *val, const TX *x, TY *y, hipStream_t s) {
                        int(A.nblk), y);
 }
 
+template <typename T>
+void to_field_major(const FieldBlockView &A, const T *src, T *dst, hipStream_t s) {
+    const int64_t n = 4 * (A.Ni + A.Ne);
+    if (n == 0) return;
+    hipLaunchKernelGGL((k_to_field_major<T>), dim3(stream_grid(n)), dim3(TPB), 0, s, A.Ni, A.Ne, src, dst);
+}
+
 template <typename TX>
 void spmv_vtx(const VtxView &A, const double *val, const TX *x, double *y, hipStream_t s) {
     if (A.nblk == 0) return;
@@ -660,6 +679,8 @@ void sub(int64_t n, const double *a, const double *b, double *y, hipStream_t s) 
 }
 
 // explicit instantiations
+template void to_field_major<double>(const FieldBlockView &, const double *, double *, hipStream_t);
+template void to_field_major<float>(const FieldBlockView &, const float *, float *, hipStream_t);
 template void spmv_vtx<double>(const VtxView &, const double *, const double *, double *, hipStream_t);
 template void spmv_vtx<float>(const VtxView &, const double *, const float *, double *, hipStream_t);
 template void spmv<double, double, double>(const CsrView &, const double *, const double *, double *, hipStream_t);

@@ -133,8 +133,8 @@ def _hptr(a):
     return a.ctypes.data_as(C.c_void_p)
 
 
-def amg_opts(precision=0, strength=0.6, cheb_degree=3, cheb_ratio=2.5, coarse_max=2000, max_levels=20,
-             coarse_drop=0.01, cheb_pre_degree=1, coarse_pre_degree=0, coarse_post_degree=1):
+def amg_opts(precision=0, strength=0.6, cheb_degree=5, cheb_ratio=2.5, coarse_max=2000, max_levels=20,
+             coarse_drop=0.01, cheb_pre_degree=0, coarse_pre_degree=0, coarse_post_degree=1):
     return AmgOpts(precision, strength, cheb_degree, cheb_ratio, coarse_max, max_levels, coarse_drop,
                    cheb_pre_degree, coarse_pre_degree, coarse_post_degree)
 
