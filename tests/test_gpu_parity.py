@@ -205,6 +205,45 @@ def test_vcycle_is_linear_and_contracts(solver3d):
     assert ratio < 0.8, ratio
 
 
+# Every V-cycle code path, not only the defaults: exact Galerkin levels with the
+# symmetric degree-3 cycle, pre-smoothing on every level, FP32 levels.  Each must
+# precondition a step-1 solve (the noisy first step) to the oracle's solution.
+AMG_VARIANTS = {
+    "default_fp64": dict(),
+    "default_fp32": dict(precision=1),
+    "galerkin_symmetric3": dict(strength=0.25, coarse_drop=0.0, cheb_degree=3, cheb_pre_degree=3,
+                                coarse_pre_degree=3, coarse_post_degree=3),
+    "presmooth_everywhere": dict(cheb_degree=3, cheb_pre_degree=1, coarse_pre_degree=1, coarse_post_degree=2),
+}
+
+
+@pytest.fixture(scope="module")
+def lattice_step1():
+    case = config_case(3, per_pitch=4, n_steps=1)
+    return case, timeloop.run(case, n_steps=1)["u"][1]
+
+
+@pytest.mark.parametrize("name", list(AMG_VARIANTS))
+def test_amg_variants_solve_to_oracle(name, lattice_step1):
+    case, ref = lattice_step1
+    s = KnpSolver(case, amg=amg_opts(**AMG_VARIANTS[name]), solve=solve_opts(**PARITY))
+    info = s.step()
+    assert info.rel_res <= PARITY["rtol"], (info.its, info.rel_res)
+    err = block_err(s.info, s.u.cpu().numpy(), ref)
+    assert max(err.values()) <= 1e-8, err
+
+
+def test_coarse_drop_thins_the_coarse_levels(lattice_step1):
+    case, _ = lattice_step1
+    nnz = {}
+    for d in (0.0, 0.01):
+        s = KnpSolver(case, amg=amg_opts(coarse_drop=d))
+        s.assemble(1)
+        nnz[d] = s.ctx.amg_stats()["nnz"]
+    assert nnz[0.0][0] == nnz[0.01][0]           # the finest level is P_0 itself
+    assert nnz[0.01][1] < nnz[0.0][1], nnz
+
+
 def test_gmres_iterates_match_oracle():
     """The k-th GMRES iterate is the unique residual minimiser over the Krylov
     space; without a preconditioner GPU and oracle iterates agree."""
