@@ -793,7 +793,16 @@ T *vcycle_level(Amg &amg, size_t l, const T *b, hipStream_t s, Timers *tm, T *ou
     const int64_t n = L->n;
     const bool fbl = l == 0;     // level 0 is P_0 in the field-block layout
     const T *av = fbl ? LV<T>::FB(L) : LV<T>::A(L);
-    T *x = LV<T>::x(L), *x2 = LV<T>::x2(L), *d = LV<T>::d(L), *t = LV<T>::t(L);
+    T *t = LV<T>::t(L);
+    // the Chebyshev recurrence in x alone (x_{k+1} from x_k and x_{k-1}) rotates three
+    // buffers; cur = x_k and prev = x_{k-1}, null standing for the zero vector
+    T *const buf[3] = {LV<T>::x(L), LV<T>::x2(L), LV<T>::d(L)};
+    T *cur = nullptr, *prev = nullptr;
+    auto spare = [&]() -> T * {
+        for (T *p : buf)
+            if (p != cur && p != prev) return p;
+        return nullptr;   // unreachable: three buffers, two in use
+    };
     // algorithmic bytes: values + column indices once, row pointers, each vector once
     const double vb = double(sizeof(T));
     const double mat = fbl ? double(L->fb.nnz) * (4.0 * vb + 4.0) + 8.0 * double(L->fb.nv + 1)
@@ -801,29 +810,28 @@ T *vcycle_level(Amg &amg, size_t l, const T *b, hipStream_t s, Timers *tm, T *ou
     Timers *t0 = (l == 0) ? tm : nullptr;
     // the finest level's timer class holds the steps that apply the operator (the
     // first step from x = 0 is a plain vector update)
-    auto cheb = [&](const T *xin, T *xout, double c1, double c2) {
-        Timers *tc = xin ? t0 : nullptr;
+    auto cheb = [&](T *xout, double c1, double c2) {
+        Timers *tc = cur ? t0 : nullptr;
         hipEvent_t e = tc ? tc->begin(KNP_TIMER_CHEB_L0, s) : nullptr;
         if (fbl)
-            launch::fb_cheb_step<T>(L->fb.view(), av, xin, b, d, xout, c1, c2, s);
+            launch::fb_cheb_step<T>(L->fb.view(), av, cur, b, prev, xout, c1, c2, s);
         else
-            launch::cheb_step<T>(L->A.view(), av, xin, b, d, xout, c1, c2, s);
-        if (tc) tc->end(KNP_TIMER_CHEB_L0, e, mat + vb * double(n) * (c1 != 0.0 ? 5.0 : 4.0), s);
+            launch::cheb_step<T>(L->A.view(), av, cur, b, prev, xout, c1, c2, s);
+        // b, x_k (gathered and own rows), x_{k-1} when c1 != 0, x_{k+1}
+        if (tc) tc->end(KNP_TIMER_CHEB_L0, e, mat + vb * double(n) * (c1 != 0.0 ? 4.0 : 3.0), s);
+        prev = cur;
+        cur = xout;
     };
     Level *Lc = amg.levels[l + 1];
     T *bc = LV<T>::b(Lc);
     if (dpre > 0) {
         // pre-smoothing from x = 0, residual, restriction
-        cheb(nullptr, x, 0.0, cpre[0].second);
-        for (size_t k = 1; k < cpre.size(); ++k) {
-            cheb(x, x2, cpre[k].first, cpre[k].second);
-            std::swap(x, x2);
-        }
+        for (size_t k = 0; k < cpre.size(); ++k) cheb(spare(), cpre[k].first, cpre[k].second);
         hipEvent_t e = t0 ? t0->begin(KNP_TIMER_RESID_L0, s) : nullptr;
         if (fbl)
-            launch::fb_residual<T>(L->fb.view(), av, x, b, t, s);
+            launch::fb_residual<T>(L->fb.view(), av, cur, b, t, s);
         else
-            launch::residual<T>(L->A.view(), av, x, b, t, s);
+            launch::residual<T>(L->A.view(), av, cur, b, t, s);
         if (t0) t0->end(KNP_TIMER_RESID_L0, e, mat + 3.0 * vb * double(n), s);
         launch::spmv<T, T, T>(L->R.view(), LV<T>::R(L), t, bc, s);
     } else {
@@ -837,18 +845,17 @@ T *vcycle_level(Amg &amg, size_t l, const T *b, hipStream_t s, Timers *tm, T *ou
         }
     }
     T *xc = vcycle_level<T>(amg, l + 1, bc, s, tm);
-    if (dpre > 0)
-        launch::prolong_add<T>(L->P.view(), LV<T>::P(L), xc, x, s);
-    else
-        launch::spmv<T, T, T>(L->P.view(), LV<T>::P(L), xc, x, s);   // x = P xc
-    // post-smoothing; the last step writes to `out` when given
-    for (size_t k = 0; k < cc.size(); ++k) {
-        T *dst = (out && k + 1 == cc.size()) ? out : x2;
-        cheb(x, dst, cc[k].first, cc[k].second);
-        x2 = x;
-        x = dst;
+    if (dpre > 0) {
+        launch::prolong_add<T>(L->P.view(), LV<T>::P(L), xc, cur, s);
+    } else {
+        cur = spare();
+        launch::spmv<T, T, T>(L->P.view(), LV<T>::P(L), xc, cur, s);   // x = P xc
     }
-    return x;
+    // post-smoothing, a recurrence of its own (its first step has c1 = 0); the last
+    // step writes to `out` when given
+    prev = nullptr;
+    for (size_t k = 0; k < cc.size(); ++k) cheb((out && k + 1 == cc.size()) ? out : spare(), cc[k].first, cc[k].second);
+    return cur;
 }
 
 }  // namespace

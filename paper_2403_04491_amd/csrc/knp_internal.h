@@ -341,9 +341,10 @@ void spmv_vtx(const VtxView &A, const double *val, const TX *x, double *y, hipSt
 // y = b - A x
 template <typename T>
 void residual(const CsrView &A, const T *val, const T *x, const T *b, T *y, hipStream_t s);
-// Chebyshev step: x_out = x_in + d_new, d_new = c1 d + c2 (b - A x_in)  (x_in null => x_in = 0)
+// Chebyshev step in x alone: x_out = x_in + c1 (x_in - x_prev) + c2 (b - A x_in);
+// x_in null: the first step from x = 0, x_out = c2 b; x_prev null: the zero vector
 template <typename T>
-void cheb_step(const CsrView &A, const T *val, const T *x_in, const T *b, T *d, T *x_out, double c1,
+void cheb_step(const CsrView &A, const T *val, const T *x_in, const T *b, const T *x_prev, T *x_out, double c1,
                double c2, hipStream_t s);
 // x += P xc
 template <typename T>
@@ -354,8 +355,8 @@ void prolong_add(const CsrView &P, const T *val, const T *xc, T *x, hipStream_t 
 template <typename T>
 void fb_residual(const FieldBlockView &A, const T *val, const T *x, const T *b, T *y, hipStream_t s);
 template <typename T>
-void fb_cheb_step(const FieldBlockView &A, const T *val, const T *x_in, const T *b, T *d, T *x_out, double c1,
-                  double c2, hipStream_t s);
+void fb_cheb_step(const FieldBlockView &A, const T *val, const T *x_in, const T *b, const T *x_prev, T *x_out,
+                  double c1, double c2, hipStream_t s);
 // a level-0 vector into field-major order (the restriction's column order)
 template <typename T>
 void to_field_major(const FieldBlockView &A, const T *src, T *dst, hipStream_t s);

@@ -130,17 +130,20 @@ struct EpiResidual {
     __device__ void operator()(int32_t row, A s) const { y[row] = T(A(b[row]) - s); }
 };
 
+// Chebyshev step in x alone: x_out = x_in + c1 (x_in - x_prev) + c2 (b - A x_in), where
+// x_in - x_prev is the previous step's update; x_prev is read only when c1 != 0, and a
+// null x_prev is the zero vector
 template <typename T, typename A>
 struct EpiCheb {
-    const T *xin, *b;
-    T *d, *xout;
+    const T *xin, *xprev, *b;
+    T *xout;
     A c1, c2;
-    bool use_d;
+    bool use_prev;
     __device__ void operator()(int32_t row, A s) const {
+        const A xi = A(xin[row]);
         const A r = A(b[row]) - s;
-        const A dn = (use_d ? c1 * A(d[row]) : A(0)) + c2 * r;
-        d[row] = T(dn);
-        xout[row] = T(A(xin[row]) + dn);
+        const A dn = (use_prev ? c1 * (xi - (xprev ? A(xprev[row]) : A(0))) : A(0)) + c2 * r;
+        xout[row] = T(xi + dn);
     }
 };
 
@@ -173,22 +176,19 @@ template <typename T>
 __global__ void __launch_bounds__(TPB) k_cheb(const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col,
                                               const T *__restrict__ val, const T *__restrict__ xin,
                                               const int32_t *__restrict__ blk, int nblk, const T *__restrict__ b,
-                                              T *__restrict__ d, T *__restrict__ xout, double c1, double c2) {
+                                              const T *__restrict__ xprev, T *__restrict__ xout, double c1,
+                                              double c2) {
     using A = typename Acc<T>::type;
-    EpiCheb<T, A> e{xin, b, d, xout, A(c1), A(c2), c1 != 0.0};
+    EpiCheb<T, A> e{xin, xprev, b, xout, A(c1), A(c2), c1 != 0.0};
     stream_rows<T, T, A>(rowptr, col, val, xin, blk, nblk, e);
 }
 
-// first Chebyshev step from x = 0: d = c2 b, x = d (no operator application)
+// first Chebyshev step from x = 0: x = c2 b (no operator application)
 template <typename T>
-__global__ void k_cheb_first(int64_t n, const T *__restrict__ b, T *__restrict__ d, T *__restrict__ xout,
-                             double c2) {
+__global__ void k_cheb_first(int64_t n, const T *__restrict__ b, T *__restrict__ xout, double c2) {
     using A = typename Acc<T>::type;
-    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
-        const T v = T(A(c2) * A(b[i]));
-        d[i] = v;
-        xout[i] = v;
-    }
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+        xout[i] = T(A(c2) * A(b[i]));
 }
 
 template <typename T>
@@ -294,9 +294,10 @@ __global__ void __launch_bounds__(TPB) k_fb_residual(FieldBlockView fb, const T 
 template <typename T>
 __global__ void __launch_bounds__(TPB) k_fb_cheb(FieldBlockView fb, const T *__restrict__ val,
                                                  const T *__restrict__ xin, const T *__restrict__ b,
-                                                 T *__restrict__ d, T *__restrict__ xout, double c1, double c2) {
+                                                 const T *__restrict__ xprev, T *__restrict__ xout, double c1,
+                                                 double c2) {
     using A = typename Acc<T>::type;
-    FbCheb<T, A> e{EpiCheb<T, A>{xin, b, d, xout, A(c1), A(c2), c1 != 0.0}};
+    FbCheb<T, A> e{EpiCheb<T, A>{xin, xprev, b, xout, A(c1), A(c2), c1 != 0.0}};
     stream_field_blocks<T, A>(fb, val, xin, e);
 }
 
@@ -585,15 +586,15 @@ void residual(const CsrView &A, const T *val, const T *x, const T *b, T *y, hipS
 }
 
 template <typename T>
-void cheb_step(const CsrView &A, const T *val, const T *x_in, const T *b, T *d, T *x_out, double c1, double c2,
-               hipStream_t s) {
+void cheb_step(const CsrView &A, const T *val, const T *x_in, const T *b, const T *x_prev, T *x_out, double c1,
+               double c2, hipStream_t s) {
     if (A.nrows == 0) return;
     if (!x_in) {
-        hipLaunchKernelGGL((k_cheb_first<T>), dim3(stream_grid(A.nrows)), dim3(TPB), 0, s, A.nrows, b, d, x_out, c2);
+        hipLaunchKernelGGL((k_cheb_first<T>), dim3(stream_grid(A.nrows)), dim3(TPB), 0, s, A.nrows, b, x_out, c2);
         return;
     }
     hipLaunchKernelGGL((k_cheb<T>), dim3(block_grid(A.nblk)), dim3(TPB), 0, s, A.rowptr, A.col, val, x_in, A.blk,
-                       int(A.nblk), b, d, x_out, c1, c2);
+                       int(A.nblk), b, x_prev, x_out, c1, c2);
 }
 
 template <typename T>
@@ -603,16 +604,16 @@ void fb_residual(const FieldBlockView &A, const T *val, const T *x, const T *b, 
 }
 
 template <typename T>
-void fb_cheb_step(const FieldBlockView &A, const T *val, const T *x_in, const T *b, T *d, T *x_out, double c1,
-                  double c2, hipStream_t s) {
+void fb_cheb_step(const FieldBlockView &A, const T *val, const T *x_in, const T *b, const T *x_prev, T *x_out,
+                  double c1, double c2, hipStream_t s) {
     const int64_t n = 4 * (A.Ni + A.Ne);
     if (n == 0) return;
     if (!x_in) {
-        hipLaunchKernelGGL((k_cheb_first<T>), dim3(stream_grid(n)), dim3(TPB), 0, s, n, b, d, x_out, c2);
+        hipLaunchKernelGGL((k_cheb_first<T>), dim3(stream_grid(n)), dim3(TPB), 0, s, n, b, x_out, c2);
         return;
     }
-    hipLaunchKernelGGL((k_fb_cheb<T>), dim3(block_grid(A.nblk)), dim3(TPB), 0, s, A, val, x_in, b, d, x_out, c1,
-                       c2);
+    hipLaunchKernelGGL((k_fb_cheb<T>), dim3(block_grid(A.nblk)), dim3(TPB), 0, s, A, val, x_in, b, x_prev, x_out,
+                       c1, c2);
 }
 
 template <typename T>
@@ -689,17 +690,17 @@ template void spmv<float, float, float>(const CsrView &, const float *, const fl
 template void residual<double>(const CsrView &, const double *, const double *, const double *, double *,
                                hipStream_t);
 template void residual<float>(const CsrView &, const float *, const float *, const float *, float *, hipStream_t);
-template void cheb_step<double>(const CsrView &, const double *, const double *, const double *, double *, double *,
-                                double, double, hipStream_t);
-template void cheb_step<float>(const CsrView &, const float *, const float *, const float *, float *, float *, double,
-                               double, hipStream_t);
+template void cheb_step<double>(const CsrView &, const double *, const double *, const double *, const double *,
+                                double *, double, double, hipStream_t);
+template void cheb_step<float>(const CsrView &, const float *, const float *, const float *, const float *, float *,
+                               double, double, hipStream_t);
 template void fb_residual<double>(const FieldBlockView &, const double *, const double *, const double *, double *,
                                   hipStream_t);
 template void fb_residual<float>(const FieldBlockView &, const float *, const float *, const float *, float *,
                                  hipStream_t);
-template void fb_cheb_step<double>(const FieldBlockView &, const double *, const double *, const double *, double *,
-                                   double *, double, double, hipStream_t);
-template void fb_cheb_step<float>(const FieldBlockView &, const float *, const float *, const float *, float *,
+template void fb_cheb_step<double>(const FieldBlockView &, const double *, const double *, const double *,
+                                   const double *, double *, double, double, hipStream_t);
+template void fb_cheb_step<float>(const FieldBlockView &, const float *, const float *, const float *, const float *,
                                   float *, double, double, hipStream_t);
 template void prolong_add<double>(const CsrView &, const double *, const double *, double *, hipStream_t);
 template void prolong_add<float>(const CsrView &, const float *, const float *, float *, hipStream_t);
