@@ -720,13 +720,43 @@ void amg_build(Amg &amg, const HostMesh &m, const std::vector<double> &p0_vals, 
     amg.cb64.alloc(std::max<int64_t>(1, nC));
     amg.cx64.alloc(std::max<int64_t>(1, nC));
     hip_check(hipStreamSynchronize(s), "amg upload");
+    // algorithmic bytes of one V-cycle: every matrix and vector each of its kernels
+    // touches, once per kernel
+    {
+        const double vb = amg.fp32 ? 4.0 : 8.0;
+        auto csr = [&](const DevCsr &M) { return double(M.nnz) * (vb + 4.0) + 8.0 * double(M.nrows + 1); };
+        double bytes = amg.fp32 ? 12.0 * double(amg.levels[0]->n) : 0.0;   // FP64 input to FP32
+        for (size_t l = 0; l + 1 < amg.levels.size(); ++l) {
+            const Level *L = amg.levels[l];
+            const double n = double(L->n), nc = double(amg.levels[l + 1]->n);
+            const double mat = l == 0 ? double(L->fb.nnz) * (4.0 * vb + 4.0) + 8.0 * double(L->fb.nv + 1) : csr(L->A);
+            const int dpre = l == 0 ? amg.pre_degree : amg.coarse_pre;
+            const int dpost = l == 0 ? amg.degree : amg.coarse_post;
+            if (dpre > 0) {
+                bytes += 2.0 * vb * n;                                      // first step from x = 0
+                for (int k = 1; k < dpre; ++k) bytes += mat + 4.0 * vb * n;
+                bytes += mat + 3.0 * vb * n;                                // residual
+            } else if (l == 0) {
+                bytes += 2.0 * vb * n;                                      // b to field-major order
+            }
+            bytes += csr(L->R) + vb * (n + nc);                             // restriction
+            bytes += csr(L->P) + vb * (nc + n) + (dpre > 0 ? vb * n : 0.0); // prolongation (+ x read)
+            bytes += mat + 3.0 * vb * n;                                    // post-smoothing, c1 = 0
+            for (int k = 1; k < dpost; ++k) bytes += mat + 4.0 * vb * n;
+        }
+        const double ncst = double(nC);
+        bytes += 8.0 * double(tot) + 16.0 * ncst;                           // dense coarsest solve
+        if (amg.fp32) bytes += 24.0 * ncst;                                 // its FP32 <-> FP64 copies
+        amg.vcycle_bytes = bytes;
+    }
     amg.ready = true;
 }
 
 namespace {
 
 // Chebyshev coefficients (c1, c2) of the three-term recurrence for the interval
-// [lmax/ratio, lmax]:  d <- c1 d + c2 r,  x <- x + d.
+// [lmax/ratio, lmax]:  x_{k+1} = x_k + c1 (x_k - x_{k-1}) + c2 (b - A x_k); c1 = 0 in
+// the first step.
 void cheb_coeffs(double lmax, double ratio, int degree, std::vector<std::pair<double, double>> &out) {
     const double a = lmax / ratio, b = lmax;
     const double theta = 0.5 * (b + a), delta = 0.5 * (b - a), sigma = theta / delta;
@@ -874,7 +904,7 @@ void amg_vcycle(Amg &amg, const double *v, void *z, hipStream_t s, Timers *tm) {
         double *x = vcycle_level<double>(amg, 0, v, s, tm, zd);
         if (x != zd) hip_check(hipMemcpyAsync(z, x, size_t(n) * sizeof(double), hipMemcpyDeviceToDevice, s), "copy");
     }
-    if (tm) tm->end(KNP_TIMER_VCYCLE, e, 0.0, s);
+    if (tm) tm->end(KNP_TIMER_VCYCLE, e, amg.vcycle_bytes, s);
 }
 
 }  // namespace knp

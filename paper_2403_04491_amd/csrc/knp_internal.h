@@ -253,6 +253,7 @@ struct Amg {
     DArray<double> cb64, cx64;       // coarse rhs / solution in FP64
     int64_t n_blocks = 0;
     std::vector<int64_t> level_nnz, level_n;
+    double vcycle_bytes = 0.0;       // algorithmic bytes of one V-cycle (its timer class)
     ~Amg();
     void clear();
 };
