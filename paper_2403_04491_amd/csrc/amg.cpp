@@ -14,9 +14,12 @@
 // couplings between them.  The coarsest level is solved with one dense FP64
 // inverse per connected component.
 //
-// Apply (device): V-cycle with Chebyshev pre/post smoothing, residual,
-// restriction and prolongation as fused CSR kernels, in FP64 or FP32 (FP32
-// accumulation); the coarsest solve is always FP64.
+// Apply (device): V-cycle with Chebyshev smoothing (a recurrence in x alone) of a
+// chosen degree before and after the coarse correction, separately for the finest
+// level (field-block kernels) and the coarser ones (block-streamed CSR); degree 0
+// before restricts the right-hand side as it is.  Residual, restriction and
+// prolongation are fused CSR kernels; FP64 or FP32 (FP32 accumulation); the
+// coarsest solve is always FP64.
 #include <omp.h>
 
 #include <algorithm>
@@ -51,8 +54,6 @@ Csr transpose(const Csr &A) {
     return T;
 }
 
-// C = A B, rows computed independently (deterministic: accumulation follows the
-// order of A's row and B's rows); columns sorted per row.
 // Drops the couplings of a coarse operator with |a_ij| < tol sqrt(a_ii a_jj) and
 // adds a_ij b_j / b_i to a_ii (b the coarse near-nullspace vector), so that A b is
 // unchanged; the criterion is symmetric, so the result stays symmetric.  If that
@@ -100,6 +101,8 @@ void sparsify(Csr &A, const std::vector<double> &b, double tol) {
     A = std::move(K);
 }
 
+// C = A B, rows computed independently (deterministic: accumulation follows the
+// order of A's row and B's rows); columns sorted per row.
 Csr spgemm(const Csr &A, const Csr &B) {
     Csr C;
     C.nrows = A.nrows;

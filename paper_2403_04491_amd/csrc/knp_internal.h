@@ -229,7 +229,8 @@ struct Level {
     double lmax = 2.0;           // spectral radius estimate of the (unit-diagonal) operator
     DevCsr A, P, R;              // P: n x n_coarse, R = P^T (A unused on level 0)
     DevFieldBlock fb;            // level 0 only: P_0 in the field-block layout
-    // level vectors (precision of the hierarchy); x2 is the Chebyshev ping-pong buffer
+    // level vectors (precision of the hierarchy); x, x2 and d are the three buffers the
+    // Chebyshev recurrence in x rotates through, t the residual
     DArray<double> b64, x64, x2_64, t64, d64;
     DArray<float> b32, x32, x2_32, t32, d32;
 };
@@ -333,7 +334,7 @@ void rows_to_external(int64_t N, const int64_t *rowptr, const int64_t *rstart, c
 void scaling_from_diag(int64_t N, const double *vals, const int64_t *diag_pos, double *sc, hipStream_t s);
 void gather(int64_t n, const double *src, const int64_t *map, double *dst, hipStream_t s);
 
-// sparse and dense linear algebra (block-streamed CSR)
+// sparse and dense linear algebra
 template <typename TM, typename TX, typename TY>
 void spmv(const CsrView &A, const TM *val, const TX *x, TY *y, hipStream_t s);
 // y = A x for the system matrix by vertex (FP64 values and result)

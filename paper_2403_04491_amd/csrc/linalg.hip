@@ -1,11 +1,12 @@
-// Sparse and dense linear-algebra kernels of the solver: CSR SpMV with fused
-// epilogues (residual, Chebyshev step, prolongation-add), the coarsest-level
-// dense solve, and the Krylov vector kernels with deterministic two-stage
-// reductions (classical Gram-Schmidt multi-dot and update, norms, axpys).
+// Sparse and dense linear-algebra kernels of the solver: the system matrix
+// streamed by vertex (k_spmv_vtx), the finest AMG level in its field-block layout
+// (stream_field_blocks), block-streamed CSR with fused epilogues (residual,
+// Chebyshev step, prolongation-add) for the coarser levels and the transpose, the
+// coarsest-level dense solve, and the Krylov vector kernels with deterministic
+// two-stage reductions (classical Gram-Schmidt multi-dot and update, norms, axpys).
 //
-// SpMV streams blocks of whole rows (see stream_rows).  All work is HBM-bound;
-// nothing here is a dense contraction, so no matrix-core instructions are
-// involved.
+// All work is HBM-bound; nothing here is a dense contraction, so no matrix-core
+// instructions are involved.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
