@@ -26,7 +26,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 __all__ = ["Case", "physical_params", "model_a_case", "lattice_case", "config_case",
-           "structured_simplex_mesh", "CONFIG_NAMES"]
+           "structured_simplex_mesh", "CONFIG_NAMES", "MEMBRANE_CODES"]
 
 
 def physical_params() -> dict:
@@ -55,6 +55,9 @@ def physical_params() -> dict:
         "conc_i0": [12.0, 125.0, 137.0],    # mol/m^3
         "conc_e0": [100.0, 4.0, 104.0],     # mol/m^3
         "n_ode": 25,
+        "rho_pump": 1.115e-6,  # mol/(m^2 s), Na/K pump maximum rate
+        "P_Na": 10.0,          # mol/m^3, ICS Na+ pump threshold
+        "P_K": 1.5,            # mol/m^3, ECS K+ pump threshold
     }
 
 
@@ -69,7 +72,7 @@ class Case:
     elem: np.ndarray             # int32 [n_elem, dim+1]
     tag: np.ndarray              # int32 [n_elem]; 0 = extracellular, c >= 1 = cell c
     cell_box: np.ndarray         # int64 [n_cells, 2, dim]: grid-index lo, hi per axis
-    cell_model: np.ndarray       # int32 [n_cells]; 0 = passive leak, 1 = Hodgkin-Huxley
+    cell_model: np.ndarray       # int32 [n_cells]; 0 = passive leak, 1 = Hodgkin-Huxley, 2 = Kir-Na/K
     cell_stim: np.ndarray        # int32 [n_cells]; 1 = periodic Na stimulus applies
     theta: np.ndarray            # float64 [n_cells]; multiplies all leak conductances of cell
     conc0: np.ndarray            # float64 [2, 3, n_vert]; region (i, e) x ion x vertex
@@ -179,9 +182,16 @@ def _strict_ecs_vertices(shape, boxes):
     return np.nonzero(ok)[0]
 
 
+MEMBRANE_CODES = {"leak": 0, "hh": 1, "kir": 2}
+
+
 def model_a_case(dim=2, nx=32, membrane="leak", dt=1e-4, n_steps=10, cfg_id=1,
                  stim=None, name=None):
-    """Model A: [0,1]^d um with one cell [0.25,0.75]^d um (Sec. "Model A")."""
+    """Model A: [0,1]^d um with one cell [0.25,0.75]^d um (Sec. "Model A").
+
+    membrane: "leak", "hh" or "kir" (the Kir-Na/K passive model); the stimulus
+    defaults to on for "hh" only.
+    """
     if nx % 4 != 0:
         raise ValueError("nx must be divisible by 4 so the cell faces lie on grid planes")
     params = physical_params()
@@ -196,7 +206,7 @@ def model_a_case(dim=2, nx=32, membrane="leak", dt=1e-4, n_steps=10, cfg_id=1,
     return Case(
         name=name or f"modelA_{dim}d_nx{nx}_{membrane}", dim=dim, shape=shape,
         length_um=(1.0,) * dim, xyz=xyz, elem=elem, tag=tag, cell_box=boxes,
-        cell_model=np.array([1 if hh else 0], np.int32),
+        cell_model=np.array([MEMBRANE_CODES[membrane]], np.int32),
         cell_stim=np.array([1 if stim else 0], np.int32),
         theta=np.ones(1), conc0=_initial_concentrations(params, xyz.shape[0], seeds["conc"]),
         phi0=(params["phi_M0"], 0.0), params=params, dt=dt, n_steps=n_steps, seeds=seeds)
@@ -204,7 +214,7 @@ def model_a_case(dim=2, nx=32, membrane="leak", dt=1e-4, n_steps=10, cfg_id=1,
 
 def lattice_case(cells=(4, 4, 4), pitch_um=(1.0, 1.0, 1.0), per_pitch=33, n_hh=16,
                  dt=5e-5, n_steps=50, cfg_id=3, theta_range=None, n_probes=0,
-                 name=None):
+                 name=None, passive="leak"):
     """Box containing a lattice of jittered box cells on a structured tet grid.
 
     Per cell (lexicographic lattice order, x fastest), with PCG64(1000+cfg): a
@@ -212,7 +222,8 @@ def lattice_case(cells=(4, 4, 4), pitch_um=(1.0, 1.0, 1.0), per_pitch=33, n_hh=1
     U(-0.05, 0.05)*pitch.  Faces are snapped to the nearest grid plane and at
     least one interval of extracellular space is kept between cells and from the
     outer boundary.  HH cells: a PCG64(3000+cfg) choice of exactly n_hh cells
-    (stimulated); the rest use the passive leak model.  Leak factors theta:
+    (stimulated); the rest use the passive model named by `passive` ("leak" or
+    "kir", the Kir-Na/K model).  Leak factors theta:
     log-uniform in theta_range from PCG64(4000+cfg) (or all 1).  Probes: the same
     generator then picks n_probes distinct vertices strictly in the ECS, not the
     pinned vertex 0.
@@ -251,7 +262,7 @@ def lattice_case(cells=(4, 4, 4), pitch_um=(1.0, 1.0, 1.0), per_pitch=33, n_hh=1
 
     n_cells = boxes.shape[0]
     rng_mem = np.random.Generator(np.random.PCG64(3000 + cfg_id))
-    model = np.zeros(n_cells, np.int32)
+    model = np.full(n_cells, MEMBRANE_CODES[passive], np.int32)
     if n_hh:
         model[rng_mem.choice(n_cells, size=n_hh, replace=False)] = 1
     rng_par = np.random.Generator(np.random.PCG64(4000 + cfg_id))
@@ -270,7 +281,7 @@ def lattice_case(cells=(4, 4, 4), pitch_um=(1.0, 1.0, 1.0), per_pitch=33, n_hh=1
     return Case(
         name=name or f"lattice_{'x'.join(map(str, cells))}_pp{per_pitch}", dim=dim,
         shape=shape, length_um=length, xyz=xyz, elem=elem, tag=tag, cell_box=boxes,
-        cell_model=model, cell_stim=model.copy(), theta=theta,
+        cell_model=model, cell_stim=(model == 1).astype(np.int32), theta=theta,
         conc0=_initial_concentrations(params, xyz.shape[0], 2000 + cfg_id),
         phi0=(params["phi_M0"], 0.0), params=params, dt=dt, n_steps=n_steps,
         probes=probes, seeds=seeds)

@@ -8,6 +8,7 @@ Sources followed (paper sections / equations):
   * tau, tilde-tau                            definition before the \\mathcal{A}_r^n display
   * alpha, C, g, h                            eq. ``weak_disc``/``weak_disc2`` and their short-hands
   * membrane currents                         eq. ``HH_ionic_model`` and the passive-leak reading
+  * Kir-Na/K currents, f_Kir, j_pump          Sec. "Passive dynamics: Kir--Na/K"
   * pinned potential                          Remark ``rem:nullspace``
 
 Readings where the text is silent or garbled (each is listed in the design notes):
@@ -18,6 +19,10 @@ Readings where the text is silent or garbled (each is listed in the design notes
   * alpha_r uses r-side concentrations; E_k uses both copies of the vertex;
     phi_M = phi_i - phi_e of the vertex pair.
   * Passive leak membrane: I_k = theta * g_leak^k (phi_M - E_k) for every ion.
+  * Kir-Na/K: [K+]_e^0 and E_K^0 are the table's initial values ([K+]_e^0 = 4 mM,
+    E_K^0 = psi/z_K ln([K+]_e^0/[K+]_i^0)), constants of the model; theta scales the
+    leak conductances (the Kir K current included) and not the pump.  A = 1 + e^0.433
+    as printed.
   * The pinned DOF is phi_e at one vertex: its row and column are zeroed except
     the diagonal, and its right-hand side is 0.
 
@@ -151,6 +156,24 @@ def rush_larsen(w, phi_M, phi_rest, dt, n_sub):
     return w
 
 
+def kir_factor(K_e, dphi_K, phi_M, E_K0, K_e0):
+    """Inward-rectifier factor f_Kir (Sec. "Passive dynamics: Kir--Na/K"): two
+    Boltzmann factors, in dphi_K = phi_M - E_K and in phi_M, normalised by their
+    values at the initial K reversal potential, times sqrt([K+]_e/[K+]_e^0)."""
+    A = 1.0 + np.exp(0.433)
+    B = 1.0 + np.exp(-(0.1186 + E_K0) / 0.0441)
+    C = 1.0 + np.exp((dphi_K + 0.0185) / 0.0425)
+    D = 1.0 + np.exp(-(0.1186 + phi_M) / 0.0441)
+    return A * B / (C * D) * np.sqrt(K_e / K_e0)
+
+
+def pump_flux(Na_i, K_e, rho, P_Na, P_K):
+    """Na/K pump flux density j_pump (same section, eq. ``pump``): saturating in the
+    ICS Na+ (exponent 1.5) and in the ECS K+ concentration."""
+    na = Na_i ** 1.5
+    return rho * na / (na + P_Na ** 1.5) * K_e / (K_e + P_K)
+
+
 def stimulus(p, t):
     """Model A periodic Na stimulus g_stim(t) = gbar exp(-(t mod tau)/a)."""
     return p["g_stim_bar"] * np.exp(-np.fmod(t, p["stim_tau"]) / p["stim_a"])
@@ -202,6 +225,15 @@ def membrane_terms(case, lay: Layout, u_prev, gates, t, dt, theta=None) -> Membr
         gcond[hh, 0] += p["gbar_Na"] * m_ ** 3 * h_
         gcond[hh, 1] += p["gbar_K"] * n_ ** 4
     I = gcond * (phiM[:, None] - E)
+    kir = model == 2
+    if np.any(kir):
+        K_e0, K_i0 = p["conc_e0"][1], p["conc_i0"][1]
+        E_K0 = psi / z[1] * np.log(K_e0 / K_i0)
+        fk = kir_factor(ce[kir, 1], phiM[kir] - E[kir, 1], phiM[kir], E_K0, K_e0)
+        jp = pump_flux(ci[kir, 0], ce[kir, 1], p["rho_pump"], p["P_Na"], p["P_K"])
+        I = I.astype(np.result_type(I, fk, jp))
+        I[kir, 0] += 3.0 * F * z[0] * jp
+        I[kir, 1] = I[kir, 1] * fk - 2.0 * F * z[1] * jp
 
     dtype = np.result_type(ci, ce, phiM, I)          # complex under complex-step perturbation
     alpha = np.empty((2,) + ci.shape, dtype=dtype)

@@ -16,7 +16,8 @@ from conftest import golden
 from knp_inputs import config_case, model_a_case
 from oracle import timeloop
 from oracle.assemble import (Assembler, bulk_coo, gamma_coo, gamma_values, hh_rates,
-                             initial_gates, initial_state, rush_larsen, p0_values)
+                             initial_gates, initial_state, kir_factor, membrane_terms,
+                             pump_flux, rush_larsen, p0_values)
 from oracle.mesh import build_layout, structural_pattern
 from oracle.solve import dense_solve, gmres, lu_solve
 
@@ -124,7 +125,13 @@ def run3d():
     return case, timeloop.run(case, n_steps=2, keep_systems=True)
 
 
-@pytest.mark.parametrize("which", ["run2d", "run3d"])
+@pytest.fixture(scope="module")
+def run3d_kir():
+    case = model_a_case(3, 8, "kir", 5e-5, 2, cfg_id=2)
+    return case, timeloop.run(case, n_steps=2, keep_systems=True)
+
+
+@pytest.mark.parametrize("which", ["run2d", "run3d", "run3d_kir"])
 def test_nullspace_unpinned(which, request):
     """The unpinned operator annihilates e = (0, 1_i, 0, 1_e) from both sides and the
     potential rows of f sum to zero (Remark on the constant-potential nullspace)."""
@@ -153,7 +160,7 @@ def _gmass(case, lay, weight=None):
     return sp.coo_matrix((gv, (gr, gc)), shape=(lay.n_vert,) * 2).tocsr()
 
 
-@pytest.mark.parametrize("which", ["run2d", "run3d"])
+@pytest.mark.parametrize("which", ["run2d", "run3d", "run3d_kir"])
 def test_invariants(which, request):
     """I1: sum_k z_k c_k is unchanged at every node (electroneutrality, eq. ``knp``).
     I2: per cell, C_m int (phi_M^n - phi_M^{n-1}) = -dt int I_ch (test w = 1 on the
@@ -312,3 +319,97 @@ def test_lu_p0_gmres_iteration_count(row):
     assert 3 <= info["its"] <= 4 and (printed == 3 or info["its"] == printed), info["its"]
     _, info0 = gmres(A, s.f, x0=u0, restart=30, rtol=1e-6, maxiter=300)
     assert info0["its"] >= 100          # unpreconditioned GMRES stalls (same section)
+
+
+# --------------------------------------------------------------------------- Kir-Na/K
+# Sec. "Passive dynamics: Kir--Na/K" and Table "Physical parameters".
+def test_kir_factor_at_both_half_activation_points():
+    """C and D are logistic factors with midpoints dphi_K = -18.5 mV and phi_M =
+    -118.6 mV, where each equals 2; with E_K^0 = -118.6 mV also B = 2 and [K+]_e =
+    [K+]_e^0 leaves f_Kir = A / 2."""
+    got = kir_factor(4.0, -0.0185, -0.1186, -0.1186, 4.0)
+    assert abs(got - (1.0 + np.exp(0.433)) / 2.0) < 1e-15
+
+
+def test_kir_factor_normalisation_and_concentration_scaling():
+    """At the initial state (phi_M = E_K = E_K^0, [K+]_e = [K+]_e^0) the factor is 1 up
+    to the rounding of 18.5/42.5 = 0.4353 to the printed 0.433; it grows as the square
+    root of [K+]_e at fixed potentials."""
+    p = config_case(1).params
+    psi = p["R"] * p["T"] / p["F"]
+    E_K0 = psi * np.log(p["conc_e0"][1] / p["conc_i0"][1])
+    f0 = kir_factor(4.0, 0.0, E_K0, E_K0, 4.0)
+    assert abs(f0 - 1.0) < 2e-3
+    for s in (0.25, 2.0, 9.0):
+        assert abs(kir_factor(4.0 * s, 0.01, -0.07, E_K0, 4.0) / kir_factor(4.0, 0.01, -0.07, E_K0, 4.0)
+                   - np.sqrt(s)) < 1e-14
+
+
+def test_kir_factor_rectifies_inward():
+    """Inward rectification: at fixed phi_M the conductance falls as the driving force
+    phi_M - E_K grows (outward current limited) and tends to a finite limit for a
+    large inward driving force; at fixed dphi_K it rises with phi_M."""
+    d = np.linspace(-0.1, 0.1, 41)
+    f = kir_factor(4.0, d, -0.07, -0.089, 4.0)
+    assert np.all(np.diff(f) < 0)
+    lim = kir_factor(4.0, -1.0, -0.07, -0.089, 4.0)
+    assert abs(lim - kir_factor(4.0, -2.0, -0.07, -0.089, 4.0)) < 1e-8 * lim
+    ph = np.linspace(-0.12, 0.0, 25)
+    assert np.all(np.diff(kir_factor(4.0, 0.0, ph, -0.089, 4.0)) > 0)
+
+
+def test_pump_flux_saturation():
+    """Half-saturation at the thresholds, the 3/2-power in [Na+]_i (4 P_Na gives
+    8/9), and the maximum rate rho_pump for large concentrations."""
+    rho, PNa, PK = 1.115e-6, 10.0, 1.5
+    assert abs(pump_flux(PNa, PK, rho, PNa, PK) - rho / 4) < 1e-15 * rho
+    assert abs(pump_flux(4 * PNa, PK, rho, PNa, PK) - rho * (8 / 9) / 2) < 1e-15 * rho
+    assert abs(pump_flux(1e12, 1e12, rho, PNa, PK) - rho) < 1e-15
+    assert pump_flux(0.0, 4.0, rho, PNa, PK) == 0.0 and pump_flux(12.0, 0.0, rho, PNa, PK) == 0.0
+
+
+def _kir_terms(g_leak=None, rho=None, model=2, at_thresholds=False):
+    case = model_a_case(2, 8, "kir", 1e-4, 1)
+    case.cell_model[:] = model
+    if g_leak is not None:
+        case.params["g_leak"] = g_leak
+    if rho is not None:
+        case.params["rho_pump"] = rho
+    lay = Assembler(case).lay
+    u0 = initial_state(case, lay)
+    if at_thresholds:      # ICS Na+ = P_Na and ECS K+ = P_K on the membrane
+        u0[lay.dof(0, 0, lay.loc[0, lay.gamma])] = case.params["P_Na"]
+        u0[lay.dof(1, 1, lay.loc[1, lay.gamma])] = case.params["P_K"]
+    return case, lay, membrane_terms(case, lay, u0, None, case.dt, case.dt)
+
+
+def test_pump_moves_three_na_out_per_two_k_in():
+    """With every channel closed only the pump acts: the Na+ and K+ membrane fluxes
+    I_k / (F z_k) are 3 j and -2 j (outward positive), Cl- carries nothing, and the
+    net current is F j_pump > 0."""
+    case, lay, mem = _kir_terms(g_leak=[0.0, 0.0, 0.0])
+    p = case.params
+    z = np.array(p["z"])
+    flux = mem.I / (p["F"] * z[None, :])
+    j = flux[:, 0] / 3.0
+    assert np.all(j > 0)
+    assert np.allclose(flux[:, 1], -2.0 * j, rtol=1e-14, atol=0)
+    assert np.all(flux[:, 2] == 0)
+    assert np.allclose(mem.I.sum(axis=1), p["F"] * j, rtol=1e-13, atol=0)
+    # the pump reads the ICS Na+ and the ECS K+: at their thresholds j = rho / 4
+    case, lay, mem = _kir_terms(g_leak=[0.0, 0.0, 0.0], at_thresholds=True)
+    j = mem.I[:, 0] / (3.0 * p["F"] * z[0])
+    assert np.allclose(j, p["rho_pump"] / 4, rtol=1e-14, atol=0)
+
+
+def test_kir_reduces_to_leak_without_pump():
+    """rho_pump = 0: Na+ and Cl- currents equal the leak model's; the K+ current is the
+    leak current times f_Kir, which is below 1 here since phi_M^0 lies above E_K."""
+    _, _, leak = _kir_terms(rho=0.0, model=0)
+    _, _, kir = _kir_terms(rho=0.0, model=2)
+    assert np.array_equal(kir.I[:, 0], leak.I[:, 0]) and np.array_equal(kir.I[:, 2], leak.I[:, 2])
+    ratio = kir.I[:, 1] / leak.I[:, 1]
+    assert np.all((ratio > 0.7) & (ratio < 0.95))
+    _, _, kirp = _kir_terms(model=2)
+    assert np.array_equal(kirp.I[:, 2], leak.I[:, 2])
+    assert np.all(kirp.I[:, 0] > leak.I[:, 0]) and np.all(kirp.I[:, 1] < kir.I[:, 1])
