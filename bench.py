@@ -388,6 +388,9 @@ def main():
     ap.add_argument("--coarse-pre-degree", type=int, default=0)
     ap.add_argument("--coarse-post-degree", type=int, default=1)
     ap.add_argument("--coarse-max", type=int, default=2000)
+    ap.add_argument("--passive", choices=["leak", "kir"], default="leak",
+                    help="membrane model of the 48 non-HH cells: passive leak, or Kir-Na/K (HH + Kir-Na/K "
+                         "as in the paper's Model D)")
     ap.add_argument("--kernels-only", action="store_true",
                     help="profiling mode: apply S A S and one V-cycle --reps times after setup, plus a "
                          "1 GiB device copy that calibrates the HBM byte counters")
@@ -433,7 +436,7 @@ def main():
     from paper_2403_04491_amd import KnpSolver, solve_opts
 
     t0 = time.perf_counter()
-    case = config_case(3, per_pitch=args.per_pitch, n_steps=args.warmup + args.steps)
+    case = config_case(3, per_pitch=args.per_pitch, n_steps=args.warmup + args.steps, passive=args.passive)
     t_gen = time.perf_counter() - t0
     log(f"case {case.name}: {case.n_vert} vertices, {case.n_elem} tets, generated in {t_gen:.1f} s")
     t0 = time.perf_counter()
@@ -481,12 +484,14 @@ def main():
         "dtype": "f64 (AMG levels f32)" if "fp32_amg" in runs else "f64",
         "data": "synthetic",
         "config": {"workload": f"4x4x4 lattice of jittered box cells, {case.shape[0]}^3 grid x 6 tets, "
-                               f"N={info.N} unknowns, 16 HH + 48 leak cells, dt=0.05 ms, FGMRES({args.restart}) rtol 1e-6",
+                               f"N={info.N} unknowns, 16 HH + 48 {'leak' if args.passive == 'leak' else 'Kir-Na/K'} cells, dt=0.05 ms, FGMRES({args.restart}) rtol 1e-6",
                    "N": info.N, "nnz_A": info.nnz_A, "nnz_P0": info.nnz_P0, "parallelism": "1 GPU",
                    "amg": amg_kw},
         "its_per_step": {k: float(sum(r["its"]) / len(r["its"])) for k, r in runs.items()},
         "steps_per_s": {k: round(r["steps_per_s"], 3) for k, r in runs.items()},
         "ms_per_step_by_precision": {k: round(r["ms_per_step"], 2) for k, r in runs.items()},
+        "assembly_ms_per_step": {k: round(r["timers"]["assembly"]["total_ms"] / max(1, r["timers"]["assembly"]["launches"]), 3)
+                                 for k, r in runs.items()},
         "amg_hierarchy": {k: r["hierarchy"] for k, r in runs.items()},
         "operator_complexity": {k: round(sum(r["hierarchy"]["nnz"]) / r["hierarchy"]["nnz"][0], 3)
                                 for k, r in runs.items()},

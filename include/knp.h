@@ -65,7 +65,9 @@ typedef struct {
 } knp_mesh_info;
 
 /* Physical parameters (Table "physconst") and membrane models
- * (eq. ``HH_ionic_model``; passive leak: every ion I_k = theta g_leak^k (phi_M - E_k)). */
+ * (eq. ``HH_ionic_model``; passive leak: every ion I_k = theta g_leak^k (phi_M - E_k);
+ * Kir-Na/K, Sec. "Passive dynamics: Kir--Na/K": leak channels with the K+ current scaled by
+ * the inward-rectifier factor f_Kir, plus the Na/K pump, 3 Na+ out per 2 K+ in). */
 typedef struct {
     double R, T, F, C_m;
     double z[3];            /* valences of Na+, K+, Cl-                           */
@@ -75,9 +77,14 @@ typedef struct {
     double g_stim_bar;      /* stimulus g_stim(t) = g_stim_bar exp(-(t mod tau)/a)*/
     double stim_a, stim_tau;
     double phi_rest;        /* HH resting potential                               */
+    double rho_pump;        /* Kir-Na/K: maximum pump rate (mol m^-2 s^-1), >= 0   */
+    double P_Na, P_K;       /* Kir-Na/K: pump thresholds of ICS Na+, ECS K+, > 0   */
+    double K_e0, K_i0;      /* Kir-Na/K: initial ECS and ICS K+ concentrations, > 0;
+                               they fix [K+]_e^0 and E_K^0 = psi/z_K ln(K_e0/K_i0) */
     int32_t n_ode;          /* Rush-Larsen sub-steps per time step                */
     int32_t n_cells;        /* must equal knp_mesh_info.n_cells                   */
-    const int32_t *cell_model;  /* host [n_cells]: 0 passive leak, 1 Hodgkin-Huxley */
+    const int32_t *cell_model;  /* host [n_cells]: 0 passive leak, 1 Hodgkin-Huxley,
+                                   2 Kir-Na/K; other values are KNP_E_ARG           */
     const int32_t *cell_stim;   /* host [n_cells]: 1 = stimulus on this cell's membrane */
 } knp_params;
 
@@ -150,7 +157,9 @@ knp_status knp_get_layout(knp_ctx *ctx, int64_t *rowptr, int32_t *colidx,
 knp_status knp_get_gamma(knp_ctx *ctx, int32_t *gamma_vertex);
 
 /* Physical parameters; copies everything it needs.  Required before the first
- * knp_assemble_step. */
+ * knp_assemble_step.  KNP_E_ARG for non-positive R, T, F, C_m or n_ode < 1, a zero
+ * valence, a non-positive diffusivity, a cell model other than 0, 1, 2, or, when some
+ * cell uses Kir-Na/K, a negative pump rate or a non-positive threshold or initial K+. */
 knp_status knp_set_params(knp_ctx *ctx, const knp_params *params);
 
 /* Assemble A_{n-1} and f_n (eq. ``lin_sys``; its block rows come from eqs.
@@ -161,7 +170,8 @@ knp_status knp_set_params(knp_ctx *ctx, const knp_params *params);
  *           (Hodgkin-Huxley cells only; other rows untouched); NULL allowed
  *           if no cell uses the Hodgkin-Huxley model;
  *   theta:  device [n_cells] factors on every leak conductance of each cell's
- *           membrane, or NULL for all 1;
+ *           membrane (the Kir-Na/K K+ current included, the pump not), or NULL
+ *           for all 1;
  *   f_out:  device [N] receives f_n (unscaled).
  * A_{n-1} stays in the context, stored as S A S with S = diag(P_0)^{-1/2} fixed
  * at the first call.  The first call also fixes P_0.  KNP_E_NUMERIC if u_prev
@@ -206,7 +216,7 @@ knp_status knp_adjoint_solve(knp_ctx *ctx, const double *rhs, double *lambda,
  * coefficients; theta through the leak currents.  Uses t_n, dt and the theta
  * pointer of the most recent knp_assemble_step, which must be the call for this
  * step (same u_prev and theta; theta must still be valid).  Passive-leak
- * membranes only (KNP_E_ARG if a Hodgkin-Huxley cell is present). */
+ * membranes only (KNP_E_ARG if a Hodgkin-Huxley or Kir-Na/K cell is present). */
 knp_status knp_step_vjp(knp_ctx *ctx, const double *u_prev, const double *u_n,
                         const double *lambda_n, double *u_prev_bar, double *theta_bar);
 

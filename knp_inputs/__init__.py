@@ -296,8 +296,10 @@ CONFIG_NAMES = {
 }
 
 
-def config_case(cfg: int, per_pitch=None, n_steps=None):
-    """The five workloads; per_pitch shrinks configs 3-5 to reduced members."""
+def config_case(cfg: int, per_pitch=None, n_steps=None, passive="leak"):
+    """The five workloads; per_pitch shrinks configs 3-5 to reduced members.  passive
+    ("leak" or "kir") is the membrane model of the lattice's non-HH cells (config 3:
+    "kir" gives the HH + Kir-Na/K mix of the paper's Model D on the same geometry)."""
     if cfg == 1:
         c = model_a_case(2, 32, "leak", 1e-4, 10, cfg_id=1, name="cfg1")
     elif cfg == 2:
@@ -305,7 +307,8 @@ def config_case(cfg: int, per_pitch=None, n_steps=None):
     elif cfg == 3:
         pp = per_pitch or 33
         c = lattice_case((4, 4, 4), (1.0, 1.0, 1.0), pp, n_hh=16, dt=5e-5, n_steps=50,
-                         cfg_id=3, name=f"cfg3_pp{pp}")
+                         cfg_id=3, name=f"cfg3_pp{pp}" + ("" if passive == "leak" else f"_{passive}"),
+                         passive=passive)
     elif cfg == 4:
         pp = per_pitch or 39
         c = lattice_case((2, 2, 2), (1.0, 1.0, 1.0), pp, n_hh=0, dt=5e-5, n_steps=40,

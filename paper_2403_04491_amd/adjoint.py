@@ -36,7 +36,7 @@ from .simulate import KnpSolver
 class AdjointProblem:
     def __init__(self, case, device=0, every=8, rtol=1e-12, adj_rtol=1e-10, restart=400, amg=None,
                  progress=None, adj_accept=None, fwd_accept=None, max_it=4000):
-        if np.any(case.cell_model == 1):
+        if np.any(case.cell_model != 0):
             raise ValueError("the adjoint supports passive-leak membranes only")
         if every < 1:
             raise ValueError("checkpoint interval must be >= 1")

@@ -171,6 +171,11 @@ knp::launch::PhysArgs knp_ctx::phys(double t, double dt) const {
     p.stim_a = prm.stim_a;
     p.stim_tau = prm.stim_tau;
     p.phi_rest = prm.phi_rest;
+    p.rho_pump = prm.rho_pump;
+    p.P_Na = prm.P_Na;
+    p.P_K = prm.P_K;
+    p.K_e0 = prm.K_e0;
+    p.E_K0 = any_kir ? psi / prm.z[1] * std::log(prm.K_e0 / prm.K_i0) : 0.0;
     p.n_ode = prm.n_ode;
     return p;
 }
@@ -556,11 +561,21 @@ knp_status knp_set_params(knp_ctx *c, const knp_params *p) {
             return fail(c, KNP_E_ARG, "invalid physical constants");
         for (int k = 0; k < 3; ++k)
             if (p->z[k] == 0.0 || !(p->D[k] > 0.0)) return fail(c, KNP_E_ARG, "invalid valence or diffusivity");
+        bool hh = false, kir = false;
+        for (int32_t i = 0; i < p->n_cells; ++i) {
+            const int32_t m = p->cell_model[i];
+            if (m < 0 || m > 2) return fail(c, KNP_E_ARG, "cell model must be 0, 1 or 2");
+            hh |= (m == 1);
+            kir |= (m == 2);
+        }
+        if (kir && !(p->rho_pump >= 0.0 && std::isfinite(p->rho_pump) && p->P_Na > 0.0 && p->P_K > 0.0 &&
+                     p->K_e0 > 0.0 && p->K_i0 > 0.0 && std::isfinite(p->P_Na + p->P_K + p->K_e0 + p->K_i0)))
+            return fail(c, KNP_E_ARG, "invalid Kir-Na/K parameters");
         c->prm = *p;
         c->cell_model.assign(p->cell_model, p->cell_model + p->n_cells);
         c->cell_stim.assign(p->cell_stim, p->cell_stim + p->n_cells);
-        c->any_hh = false;
-        for (int32_t m : c->cell_model) c->any_hh |= (m == 1);
+        c->any_hh = hh;
+        c->any_kir = kir;
         c->prm.cell_model = nullptr;
         c->prm.cell_stim = nullptr;
         std::vector<int32_t> cm = c->cell_model, cs = c->cell_stim;
@@ -805,7 +820,8 @@ knp_status knp_step_vjp(knp_ctx *c, const double *u_prev, const double *u_n, con
         need_device(c);
         if (!c->assembled) return fail(c, KNP_E_STATE, "knp_assemble_step of this step must come first");
         if (!u_prev || !u_n || !lambda_n || !u_prev_bar) return fail(c, KNP_E_ARG, "NULL vector");
-        if (c->any_hh) return fail(c, KNP_E_ARG, "vector-Jacobian products support passive-leak membranes only");
+        if (c->any_hh || c->any_kir)
+            return fail(c, KNP_E_ARG, "vector-Jacobian products support passive-leak membranes only");
         hip_check(hipSetDevice(c->device), "set device");
         const HostMesh &h = c->hm;
         hipStream_t s = c->stream;

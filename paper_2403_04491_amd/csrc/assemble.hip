@@ -39,6 +39,9 @@ __device__ inline void hh_rates(double V, double (&a)[3], double (&b)[3]) {
     b[2] = 1.0 / (exp((30.0 - V) / 10.0) + 1.0) * 1000.0;
 }
 
+// One thread per membrane vertex: channel currents I_ch^k at u_{n-1} for the cell's model
+// (0 passive leak, 1 Hodgkin-Huxley after the gating update, 2 Kir-Na/K, Sec. "Passive
+// dynamics: Kir--Na/K"), then the coefficients C_r^k, g_r^k, h_r of both regions.
 __global__ void k_membrane_coef(GammaArgs g, PhysArgs p, int64_t Ni, int64_t Ne, const double *__restrict__ u,
                                 double *__restrict__ gates, const double *__restrict__ theta,
                                 double *__restrict__ gc) {
@@ -79,13 +82,27 @@ __global__ void k_membrane_coef(GammaArgs g, PhysArgs p, int64_t Ni, int64_t Ne,
         gk[0] += p.gbar_Na * w[1] * w[1] * w[1] * w[2];
         gk[1] += p.gbar_K * w[0] * w[0] * w[0] * w[0];
     }
-    double I[3], Itot = 0.0;
+    double I[3], E[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        const double E = p.psi / p.z[k] * log(ce[k] / ci[k]);
-        I[k] = gk[k] * (phiM - E);
-        Itot += I[k];
+        E[k] = p.psi / p.z[k] * log(ce[k] / ci[k]);
+        I[k] = gk[k] * (phiM - E[k]);
     }
+    if (model == 2) {
+        // Kir-Na/K: K+ leak times the inward-rectifier factor, and the Na/K pump, which
+        // carries 3 Na+ out and 2 K+ in per cycle
+        const double A = 1.0 + exp(0.433);
+        const double B = 1.0 + exp(-(0.1186 + p.E_K0) / 0.0441);
+        const double C = 1.0 + exp((phiM - E[1] + 0.0185) / 0.0425);
+        const double D = 1.0 + exp(-(0.1186 + phiM) / 0.0441);
+        const double fkir = A * B / (C * D) * sqrt(ce[1] / p.K_e0);
+        const double na = ci[0] * sqrt(ci[0]);
+        const double pna = p.P_Na * sqrt(p.P_Na);
+        const double jp = p.rho_pump * na / (na + pna) * ce[1] / (ce[1] + p.P_K);
+        I[0] += 3.0 * p.F * p.z[0] * jp;
+        I[1] = I[1] * fkir - 2.0 * p.F * p.z[1] * jp;
+    }
+    const double Itot = I[0] + I[1] + I[2];
     double *o = gc + i * GC_STRIDE;
 #pragma unroll
     for (int r = 0; r < 2; ++r) {

@@ -43,7 +43,7 @@ struct knp_ctx {
     // parameters
     knp_params prm{};
     std::vector<int32_t> cell_model, cell_stim;
-    bool any_hh = false;
+    bool any_hh = false, any_kir = false;
 
     // device mesh data
     knp::DArray<double> d_xyz;

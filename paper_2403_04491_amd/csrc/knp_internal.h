@@ -294,6 +294,7 @@ struct PhysArgs {
     double z[3], D[3], tau[3], ttau[3];
     double F, C_m, psi, dt, t;
     double g_leak[3], gbar_Na, gbar_K, g_stim_bar, stim_a, stim_tau, phi_rest;
+    double rho_pump, P_Na, P_K, K_e0, E_K0;   // Kir-Na/K
     int n_ode;
 };
 

@@ -42,6 +42,8 @@ class Params(C.Structure):
                 ("z", C.c_double * 3), ("D", C.c_double * 3), ("g_leak", C.c_double * 3),
                 ("gbar_Na", C.c_double), ("gbar_K", C.c_double), ("g_stim_bar", C.c_double),
                 ("stim_a", C.c_double), ("stim_tau", C.c_double), ("phi_rest", C.c_double),
+                ("rho_pump", C.c_double), ("P_Na", C.c_double), ("P_K", C.c_double),
+                ("K_e0", C.c_double), ("K_i0", C.c_double),
                 ("n_ode", C.c_int32), ("n_cells", C.c_int32),
                 ("cell_model", C.POINTER(C.c_int32)), ("cell_stim", C.POINTER(C.c_int32))]
 
@@ -212,6 +214,8 @@ class Context:
         p.gbar_Na, p.gbar_K = params["gbar_Na"], params["gbar_K"]
         p.g_stim_bar, p.stim_a, p.stim_tau = params["g_stim_bar"], params["stim_a"], params["stim_tau"]
         p.phi_rest = params["phi_rest"]
+        p.rho_pump, p.P_Na, p.P_K = params["rho_pump"], params["P_Na"], params["P_K"]
+        p.K_e0, p.K_i0 = params["conc_e0"][1], params["conc_i0"][1]
         p.n_ode = int(params["n_ode"])
         p.n_cells = len(cm)
         p.cell_model = cm.ctypes.data_as(C.POINTER(C.c_int32))

@@ -115,3 +115,34 @@ def test_failed_create_reports_reason():
     assert knp.STATUS[st] == "KNP_E_HIP" and not c.value
     msg = lib.knp_last_error(None).decode()
     assert "hipGetDeviceCount" in msg or "visible" in msg, msg
+
+
+def test_ctypes_structs_match_the_header(tmp_path):
+    """Every struct of the binding has the header's size and field offsets, as the C
+    compiler lays them out (a field added on one side only fails here)."""
+    import ctypes
+    import shutil
+    import subprocess
+    from pathlib import Path
+    from paper_2403_04491_amd import knp as K
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    pairs = {"knp_mesh_info": K.MeshInfo, "knp_params": K.Params, "knp_amg_opts": K.AmgOpts,
+             "knp_solve_opts": K.SolveOpts, "knp_solve_info": K.SolveInfo, "knp_timer": K.Timer}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "knp.h"', "int main(void) {"]
+    for cname, cls in pairs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    inc = Path(__file__).resolve().parents[1] / "include"
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", f"-I{inc}", str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l}
+    for cname, cls in pairs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)

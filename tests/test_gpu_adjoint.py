@@ -111,7 +111,7 @@ def test_step_vjp_theta_entries(vjp_setup):
     assert np.abs(d["tbar"] - ref).max() <= 1e-10 * np.abs(ref).max(), (d["tbar"], ref)
 
 
-def test_step_vjp_accumulates_and_rejects_hh(vjp_setup):
+def test_step_vjp_accumulates_and_rejects_non_leak(vjp_setup):
     d = vjp_setup
     ctx = d["ctx"]
     ub = T(d["ubar"])                       # the product accumulates into u_prev_bar
@@ -129,6 +129,14 @@ def test_step_vjp_accumulates_and_rejects_hh(vjp_setup):
     z = torch.zeros(inf.N, dtype=torch.float64, device=DEV)
     with pytest.raises(knp.KnpError):
         c2.step_vjp(u, u, u, z, None)
+    c3 = knp.Context(0)                      # Kir-Na/K cells are not differentiated either
+    m = model_a_case(3, 8, "kir", 5e-5, 1, cfg_id=2)
+    inf = c3.mesh_upload(m.dim, m.xyz, m.elem, m.tag, m.pin_vertex)
+    c3.set_params(m.params, m.cell_model, m.cell_stim)
+    c3.assemble_step(m.dt, m.dt, u, None, None, f)
+    with pytest.raises(knp.KnpError) as ei:
+        c3.step_vjp(u, u, u, z, None)
+    assert ei.value.status == 1
 
 
 # ---------------------------------------------------------------------------- gradient

@@ -52,6 +52,8 @@ ASM_CASES = {
     "cfg1": lambda: config_case(1),
     "modelA3d_nx8_hh": lambda: model_a_case(3, 8, "hh", 5e-5, 2, cfg_id=2),
     "lattice4_pp4": lambda: config_case(3, per_pitch=4),
+    "modelA3d_nx8_kir": lambda: model_a_case(3, 8, "kir", 5e-5, 2, cfg_id=2),
+    "lattice4_pp4_kir": lambda: config_case(3, per_pitch=4, passive="kir"),
 }
 
 
@@ -287,6 +289,9 @@ def run_both(case, n_steps, precision=0):
     ("cfg1", 3, 1, 1e-6),
     ("modelA3d_nx8_hh", 4, 0, 1e-8),
     ("lattice4_pp4", 2, 0, 1e-8),
+    ("modelA3d_nx8_kir", 4, 0, 1e-8),
+    ("modelA3d_nx8_kir", 3, 1, 1e-6),
+    ("lattice4_pp4_kir", 2, 0, 1e-8),
 ])
 def test_time_steps_match_oracle(name, steps, precision, tol):
     case = ASM_CASES[name]()
@@ -372,6 +377,18 @@ def test_error_paths():
     with pytest.raises(knp.KnpError) as ei:
         s.ctx.amg_setup(amg_opts(precision=3))
     assert ei.value.status == 1
+    # membrane models: unknown codes and invalid Kir-Na/K parameters are argument errors;
+    # cells of other models ignore the pump parameters
+    m = model_a_case(2, 8, "kir", 1e-4, 1)
+    c3 = knp.Context(0)
+    c3.mesh_upload(m.dim, m.xyz, m.elem, m.tag, m.pin_vertex)
+    for cm, prm in ((np.array([3], np.int32), m.params), (np.array([-1], np.int32), m.params),
+                    (m.cell_model, dict(m.params, P_Na=0.0)), (m.cell_model, dict(m.params, rho_pump=-1.0)),
+                    (m.cell_model, dict(m.params, conc_i0=[12.0, 0.0, 137.0]))):
+        with pytest.raises(knp.KnpError) as ei:
+            c3.set_params(prm, cm, m.cell_stim)
+        assert ei.value.status == 1
+    c3.set_params(dict(m.params, P_Na=0.0), np.array([0], np.int32), m.cell_stim)
 
 
 def test_deterministic_rerun():
