@@ -193,6 +193,105 @@ def kernels_only(solver, args, amg_kw, log):
     print(json.dumps(out), flush=True)
 
 
+def model_a_bench(args, log):
+    """Model A's time evolution (Sec. "Model A" and the figure of iterations and run
+    times over 300 steps): the 2D unit square at N_x = 512 (N = 1,056,772), HH with the
+    periodic Na stimulus on the whole membrane, uniform initial data, 300 steps of
+    0.1 ms, FGMRES(30) + AMG(P_0) with FP32 levels at rtol 1e-6.  Step 1 (with the AMG
+    setup) is untimed; steps 2..N_t are timed one by one.  The membrane potential is
+    gathered on the device after every step; its spread over Gamma, the mean trace and
+    the spikes are reported, and the same trace for the three membrane models at
+    N_x = 64 (the paper's trace figure)."""
+    import numpy as np
+    import torch
+    from knp_inputs import model_a_evolution_case
+    from paper_2403_04491_amd import KnpSolver, amg_opts, solve_opts
+
+    def run(nx, membrane, n_steps, timed):
+        case = model_a_evolution_case(nx=nx, membrane=membrane, n_steps=n_steps)
+        s = KnpSolver(case, amg=amg_opts(precision=1), solve=solve_opts(rtol=1e-6, restart=30, max_it=2000))
+        ri, re = s.membrane_rows()
+        trace = torch.empty((n_steps + 1, ri.numel()), dtype=torch.float64, device=s.dev)
+        trace[0] = s.u[ri] - s.u[re]
+        its, times = [], []
+        t_setup = None
+        for n in range(1, n_steps + 1):
+            if n == 2 and timed:
+                s.ctx.timing(True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = s.step()
+            trace[n] = s.u[ri] - s.u[re]
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            if n == 1:
+                t_setup = dt
+            else:
+                times.append(dt)
+            its.append(info.its)
+            if not (info.rel_res <= 1e-6):
+                raise RuntimeError(f"step {n}: no convergence ({info.its} its, {info.rel_res:.2e})")
+        timers = s.ctx.timing_read() if timed else None
+        s.ctx.timing(False)
+        tr = trace.cpu().numpy()
+        return case, s, np.array(its), np.array(times), t_setup, tr, timers
+
+    nx, n_steps = args.ma_nx, args.ma_steps
+    case, s, its, times, t_first, tr, timers = run(nx, "hh", n_steps, True)
+    log(f"{case.name}: N={s.info.N}, step 1 with AMG setup {t_first:.2f} s, steps 2..{n_steps} "
+        f"{times.sum():.2f} s, iterations {its.min()}..{its.max()} (mean {its.mean():.2f})")
+    mean = tr.mean(axis=1)
+    spread = float(np.abs(tr - mean[:, None]).max())
+    per = int(round(case.params["stim_tau"] / case.dt))
+    onsets = list(range(0, n_steps, per))
+    spikes = []
+    for on in onsets:
+        seg = mean[on + 1:min(on + per, n_steps) + 1]
+        up = np.nonzero(seg > 0.0)[0]
+        spikes.append({"stimulus_ms": round(on * case.dt * 1e3, 3),
+                       "crosses_0mV_ms": None if len(up) == 0 else round((on + 1 + up[0]) * case.dt * 1e3, 3),
+                       "peak_mV": round(float(seg.max()) * 1e3, 2)})
+    kernel, roof = roofline_of(timers, "fp32_amg")
+    roof["traffic"] = None          # the counters were taken on the 132^3 lattice, not here
+    sample_steps = [0, 1, 2, 5, 10, 20, 50, 100, 101, 105, 150, 200, 205, 250, n_steps]
+    traces = {}
+    for membrane in ("hh", "kir", "leak"):
+        c2, _, its2, _, _, tr2, _ = run(args.ma_trace_nx, membrane, n_steps, False)
+        m2 = tr2.mean(axis=1)
+        traces[membrane] = {"phi_M_mV": {str(k): round(float(m2[k]) * 1e3, 2) for k in sample_steps if k <= n_steps},
+                            "min_mV": round(float(m2.min()) * 1e3, 2), "max_mV": round(float(m2.max()) * 1e3, 2),
+                            "spread_on_gamma_V": float(np.abs(tr2 - m2[:, None]).max()),
+                            "its_mean": round(float(its2.mean()), 2)}
+        log(f"  trace {membrane} at N_x={args.ma_trace_nx}: phi_M {traces[membrane]['min_mV']}.."
+            f"{traces[membrane]['max_mV']} mV")
+    hist = {str(int(k)): int(v) for k, v in zip(*np.unique(its[1:], return_counts=True))}
+    out = {
+        "metric": "Model A time evolution: time steps/s and GMRES iterations per step over 300 steps",
+        "value": round(len(times) / times.sum(), 3),
+        "unit": "time steps/s",
+        "n_gpus": 1, "steps": len(times), "warmup": 1,
+        "ms_per_step": round(1e3 * times.mean(), 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64 (AMG levels f32)", "data": "synthetic",
+        "config": {"workload": f"Model A, 2D unit square with one cell, N_x={nx}, N={s.info.N} unknowns, HH with "
+                               f"the periodic Na stimulus on Gamma, uniform initial data, dt=0.1 ms, {n_steps} steps, "
+                               f"FGMRES(30) + AMG(P_0) FP32 levels, rtol 1e-6",
+                   "N": s.info.N, "nnz_A": s.info.nnz_A, "parallelism": "1 GPU"},
+        "first_step_s": round(t_first, 3),
+        "ms_per_step_max": round(1e3 * times.max(), 3),
+        "its_per_step": {"min": int(its[1:].min()), "max": int(its[1:].max()), "mean": round(float(its[1:].mean()), 3),
+                         "step1": int(its[0]), "histogram_steps_2_on": hist},
+        "paper_its_per_step": "1-6 (LU(P_0) and AMG(P_0), 32 MPI processes, its own stopping rule)",
+        "phi_M_spread_on_gamma_V": spread,
+        "spikes": spikes,
+        "traces_nx": args.ma_trace_nx,
+        "traces": traces,
+        "roofline": roof,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def adjoint_bench(args, log):
     """Gradient of the probe objective on the 2x2x2 lattice (~2e6 unknowns): one
     checkpointed forward + reverse sweep over the full horizon, timed at the given
@@ -411,6 +510,11 @@ def main():
     ap.add_argument("--large-steps", type=int, default=9)
     ap.add_argument("--large-first-restart", type=int, default=60)
     ap.add_argument("--fd-steps", type=int, default=4, help="horizon of the finite-difference check")
+    ap.add_argument("--model-a", action="store_true",
+                    help="Model A's time evolution (2D, N_x = 512, 300 steps) instead of the step throughput")
+    ap.add_argument("--ma-nx", type=int, default=512)
+    ap.add_argument("--ma-steps", type=int, default=300)
+    ap.add_argument("--ma-trace-nx", type=int, default=64)
     ap.add_argument("--fd-rtol-fwd", type=float, default=1e-11)
     ap.add_argument("--fd-rtol-adj", type=float, default=1e-8)
     args = ap.parse_args()
@@ -427,6 +531,9 @@ def main():
         sys.exit(2)
     if args.adjoint:
         adjoint_bench(args, log)
+        return
+    if args.model_a:
+        model_a_bench(args, log)
         return
     if args.large:
         large_bench(args, log)

@@ -25,7 +25,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-__all__ = ["Case", "physical_params", "model_a_case", "lattice_case", "config_case",
+__all__ = ["Case", "physical_params", "model_a_case", "model_a_evolution_case", "lattice_case", "config_case",
            "structured_simplex_mesh", "CONFIG_NAMES", "MEMBRANE_CODES"]
 
 
@@ -152,16 +152,17 @@ def _tags_from_boxes(shape, boxes):
     return np.repeat(cube.ravel(), n_perm)
 
 
-def _initial_concentrations(params, n_vert, seed):
+def _initial_concentrations(params, n_vert, seed, noise=0.01):
     """Per-vertex initial concentrations for both regions.
 
-    Na and K are the table values times (1 + U(-0.01, 0.01)); Cl = Na + K keeps
+    Na and K are the table values times (1 + U(-noise, noise)); Cl = Na + K keeps
     every node electroneutral.  Draws: numpy PCG64(seed), one array of shape
     (region i/e, ion Na/K, vertex) for *every* grid vertex, so that the draw
-    does not depend on which vertices a region owns.
+    does not depend on which vertices a region owns.  noise = 0 gives the
+    table's uniform values.
     """
     rng = np.random.Generator(np.random.PCG64(seed))
-    u = rng.uniform(-0.01, 0.01, size=(2, 2, n_vert))
+    u = rng.uniform(-noise, noise, size=(2, 2, n_vert))
     conc = np.empty((2, 3, n_vert), dtype=np.float64)
     for r, base in enumerate((params["conc_i0"], params["conc_e0"])):
         conc[r, 0] = base[0] * (1.0 + u[r, 0])
@@ -186,11 +187,12 @@ MEMBRANE_CODES = {"leak": 0, "hh": 1, "kir": 2}
 
 
 def model_a_case(dim=2, nx=32, membrane="leak", dt=1e-4, n_steps=10, cfg_id=1,
-                 stim=None, name=None):
+                 stim=None, name=None, noise=0.01):
     """Model A: [0,1]^d um with one cell [0.25,0.75]^d um (Sec. "Model A").
 
     membrane: "leak", "hh" or "kir" (the Kir-Na/K passive model); the stimulus
-    defaults to on for "hh" only.
+    defaults to on for "hh" only.  noise: relative amplitude of the per-vertex
+    perturbation of the initial Na and K concentrations (0 = the table's values).
     """
     if nx % 4 != 0:
         raise ValueError("nx must be divisible by 4 so the cell faces lie on grid planes")
@@ -208,8 +210,17 @@ def model_a_case(dim=2, nx=32, membrane="leak", dt=1e-4, n_steps=10, cfg_id=1,
         length_um=(1.0,) * dim, xyz=xyz, elem=elem, tag=tag, cell_box=boxes,
         cell_model=np.array([MEMBRANE_CODES[membrane]], np.int32),
         cell_stim=np.array([1 if stim else 0], np.int32),
-        theta=np.ones(1), conc0=_initial_concentrations(params, xyz.shape[0], seeds["conc"]),
+        theta=np.ones(1), conc0=_initial_concentrations(params, xyz.shape[0], seeds["conc"], noise),
         phi0=(params["phi_M0"], 0.0), params=params, dt=dt, n_steps=n_steps, seeds=seeds)
+
+
+def model_a_evolution_case(nx=512, membrane="hh", n_steps=300, dt=1e-4, dim=2):
+    """Model A's time evolution (Sec. "Model A" and its iteration-count figure): the
+    2D unit square at N_x = 512 (N = 1,056,772 for p = 1), the periodic Na stimulus
+    on the whole membrane for every membrane model, the table's uniform initial
+    values, N_t = 300 steps of 0.1 ms."""
+    return model_a_case(dim, nx, membrane, dt, n_steps, cfg_id=6, stim=True, noise=0.0,
+                        name=f"modelA_evolution_{dim}d_nx{nx}_{membrane}")
 
 
 def lattice_case(cells=(4, 4, 4), pitch_um=(1.0, 1.0, 1.0), per_pitch=33, n_hh=16,

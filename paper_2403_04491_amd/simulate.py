@@ -45,6 +45,19 @@ class KnpSolver:
         self.n = 0
         self.history = []
 
+    def membrane_rows(self):
+        """Device indices (phi_i rows, phi_e rows) of the membrane vertices, in the
+        order of knp_get_gamma, so that phi_M = u[rows_i] - u[rows_e]."""
+        Ni, Ne = self.info.N_i, self.info.N_e
+        pos_i = np.full(self.case.n_vert, -1, np.int64)
+        pos_e = np.full(self.case.n_vert, -1, np.int64)
+        pos_i[self.dof_vertex[3 * Ni:4 * Ni]] = np.arange(3 * Ni, 4 * Ni)
+        pos_e[self.dof_vertex[4 * Ni + 3 * Ne:]] = np.arange(4 * Ni + 3 * Ne, 4 * Ni + 4 * Ne)
+        ri, re = pos_i[self.gamma], pos_e[self.gamma]
+        if np.any(ri < 0) or np.any(re < 0):
+            raise RuntimeError("membrane vertex without a DOF in both regions")
+        return (torch.as_tensor(ri, device=self.dev), torch.as_tensor(re, device=self.dev))
+
     def assemble(self, n=None):
         n = self.n + 1 if n is None else n
         self.ctx.assemble_step(n * self.case.dt, self.case.dt, self.u, self.gates, self.theta, self.f)

@@ -14,9 +14,9 @@ torch = pytest.importorskip("torch")
 
 pytestmark = pytest.mark.gpu
 
-from knp_inputs import config_case, model_a_case  # noqa: E402
+from knp_inputs import config_case, model_a_case, model_a_evolution_case  # noqa: E402
 from oracle import timeloop  # noqa: E402
-from oracle.assemble import Assembler, initial_gates, initial_state, p0_values  # noqa: E402
+from oracle.assemble import Assembler, gamma_values, initial_gates, initial_state, p0_values  # noqa: E402
 from oracle.solve import gmres  # noqa: E402
 from oracle.timeloop import advance_gates  # noqa: E402
 from paper_2403_04491_amd import KnpSolver, amg_opts, knp, solve_opts  # noqa: E402
@@ -303,6 +303,36 @@ def test_time_steps_match_oracle(name, steps, precision, tol):
         worst = max(worst, max(e.values()))
     print(f"  its per step {its}, worst block error {worst:.2e}", flush=True)
     assert worst <= tol
+
+
+def test_model_a_evolution_matches_oracle():
+    """Model A's time evolution (HH, stimulus every 10 ms, uniform initial data) over
+    300 steps at N_x = 32, three action potentials: every 10th state against the
+    oracle's, and the membrane potential at every step."""
+    case = model_a_evolution_case(nx=32, n_steps=300)
+    print(f"[evolution] {case.name} steps=300", flush=True)
+    ref = timeloop.run(case)
+    lay = ref["asm"].lay
+    s = KnpSolver(case, amg=amg_opts(precision=0), solve=solve_opts(**PARITY))
+    ri, re = s.membrane_rows()
+    order = np.argsort(s.gamma)
+    assert np.array_equal(s.gamma[order], np.sort(lay.gamma))
+    worst, worst_phiM, its = 0.0, 0.0, []
+    for n in range(1, 301):
+        its.append(s.step().its)
+        phiM = (s.u[ri] - s.u[re]).cpu().numpy()
+        _, _, ref_phiM = gamma_values(lay, ref["u"][n])
+        worst_phiM = max(worst_phiM, float(np.abs(phiM[order] - ref_phiM[np.argsort(lay.gamma)]).max()))
+        if n % 10 == 0:
+            e = block_err(s.info, s.u.cpu().numpy(), ref["u"][n])
+            worst = max(worst, max(e.values()))
+    print(f"  iterations min/mean/max {min(its)}/{np.mean(its):.1f}/{max(its)}, worst block error "
+          f"{worst:.2e}, worst phi_M error {worst_phiM:.2e} V", flush=True)
+    # each step's solution carries up to ~2e-10 relative error in the potentials on both
+    # sides (the rounding floor of LU on a system with cond > 1e10); over 300 steps these
+    # add up to at most 300 x 2e-10 = 6e-8
+    assert worst <= 300 * 2e-10
+    assert worst_phiM <= 1e-8 * 0.1          # 1e-8 of the 0.1 V scale of an action potential
 
 
 def test_paper_tolerance_iterations_and_error():

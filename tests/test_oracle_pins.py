@@ -13,11 +13,11 @@ import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
 from conftest import golden
-from knp_inputs import config_case, model_a_case
+from knp_inputs import config_case, model_a_case, model_a_evolution_case
 from oracle import timeloop
 from oracle.assemble import (Assembler, bulk_coo, gamma_coo, gamma_values, hh_rates,
                              initial_gates, initial_state, kir_factor, membrane_terms,
-                             pump_flux, rush_larsen, p0_values)
+                             pump_flux, rush_larsen, p0_values, stimulus)
 from oracle.mesh import build_layout, structural_pattern
 from oracle.solve import dense_solve, gmres, lu_solve
 
@@ -413,3 +413,75 @@ def test_kir_reduces_to_leak_without_pump():
     _, _, kirp = _kir_terms(model=2)
     assert np.array_equal(kirp.I[:, 2], leak.I[:, 2])
     assert np.all(kirp.I[:, 0] > leak.I[:, 0]) and np.all(kirp.I[:, 1] < kir.I[:, 1])
+
+
+# --------------------------------------------------------------------------- Model A evolution
+# Sec. "Model A": HH membrane, periodic Na stimulus on all of Gamma, uniform initial values.
+@pytest.fixture(scope="module")
+def model_a_run():
+    case = model_a_evolution_case(nx=16, n_steps=300)
+    res = timeloop.run(case)
+    phi = np.array([gamma_values(res["asm"].lay, u)[2] for u in res["u"]])
+    return case, res, phi
+
+
+def test_model_a_membrane_potential_is_homogeneous(model_a_run):
+    """The membrane potential of Model A is the same all over Gamma (the Model A figure's
+    caption): over 300 steps, three action potentials included, the spread over the
+    membrane vertices stays below 1 uV."""
+    _, _, phi = model_a_run
+    assert np.abs(phi - phi.mean(axis=1, keepdims=True)).max() < 1e-6
+
+
+def test_model_a_first_step_is_forward_euler_of_the_point_model(model_a_run):
+    """From uniform data phi_M is uniform on Gamma, and the per-cell capacitive balance
+    (I2) makes the first step one forward-Euler step of the point (0-D) HH membrane,
+    C_m (phi^1 - phi^0) = -dt I(phi^0, w_1, t_1), with w_1 after the Rush-Larsen
+    sub-steps (Sec. "Time discretization") and the stimulus at t_1."""
+    case, _, phi = model_a_run
+    p = case.params
+    psi = p["R"] * p["T"] / p["F"]
+    E = psi / np.array(p["z"]) * np.log(np.array(p["conc_e0"]) / np.array(p["conc_i0"]))
+    w1 = rush_larsen(np.array([p["gates0"]]), np.array([p["phi_M0"]]), p["phi_rest"], case.dt, p["n_ode"])[0]
+    g = np.array(p["g_leak"], dtype=float)
+    g[0] += stimulus(p, case.dt) + p["gbar_Na"] * w1[1] ** 3 * w1[2]
+    g[1] += p["gbar_K"] * w1[0] ** 4
+    expect = p["phi_M0"] - case.dt / p["C_m"] * float(g @ (p["phi_M0"] - E))
+    assert abs(phi[1].mean() - expect) < 1e-9, (phi[1].mean(), expect)
+    assert abs(phi[1].mean() - phi[0].mean()) > 0.02       # a 23 mV jump: the stimulus acts
+
+
+def test_model_a_fires_once_per_stimulus(model_a_run):
+    """Each stimulus (every tau = 10 ms = 100 steps) triggers one action potential:
+    phi_M crosses 0 mV within 1 ms of the onset, is back below -50 mV within 5 ms,
+    and stays there until the next onset."""
+    case, _, phi = model_a_run
+    m = phi.mean(axis=1)
+    per = int(round(case.params["stim_tau"] / case.dt))
+    for k in range(3):
+        on = k * per
+        assert m[on + 1:on + 11].max() > 0.0, k
+        assert m[on + 50:on + per].max() < -0.050, k
+
+
+def test_model_a_lu_p0_iterations_stay_low_over_time(model_a_run):
+    """Over the 300 steps, action potentials included, GMRES preconditioned by the exact
+    LU of P_0 needs 1-6 iterations per step (Sec. "Iterative solver robustness", the
+    figure of iterations over 300 steps) under the paper's stopping rule: the
+    left-preconditioned residual relative to the preconditioned right-hand side, from
+    the initial guess u_{n-1}.  P_0 is that of the first step, as in the paper."""
+    case, res, _ = model_a_run
+    asm = res["asm"]
+    lay = asm.lay
+    lu = None
+    its = []
+    for n in range(1, case.n_steps + 1):
+        s = asm.assemble(res["u"][n - 1], res["gates"][n], n * case.dt, case.dt)
+        A = s.csr()
+        if lu is None:
+            P0 = sp.csr_matrix((p0_values(s, lay), s.colidx, s.rowptr), shape=A.shape)
+            lu = spla.splu(sp.csc_matrix(P0))
+        _, info = gmres(lambda v: lu.solve(A @ v), lu.solve(s.f), x0=res["u"][n - 1], restart=30,
+                        rtol=1e-6, maxiter=100)
+        its.append(info["its"])
+    assert 1 <= min(its) and max(its) <= 6, (min(its), max(its))
