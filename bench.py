@@ -255,7 +255,7 @@ def model_a_bench(args, log):
     roof["traffic"] = None          # the counters were taken on the 132^3 lattice, not here
     sample_steps = [0, 1, 2, 5, 10, 20, 50, 100, 101, 105, 150, 200, 205, 250, n_steps]
     traces = {}
-    for membrane in ("hh", "kir", "leak"):
+    for membrane in (("hh", "kir", "leak") if args.ma_trace_nx > 0 else ()):
         c2, _, its2, _, _, tr2, _ = run(args.ma_trace_nx, membrane, n_steps, False)
         m2 = tr2.mean(axis=1)
         traces[membrane] = {"phi_M_mV": {str(k): round(float(m2[k]) * 1e3, 2) for k in sample_steps if k <= n_steps},
@@ -265,6 +265,44 @@ def model_a_bench(args, log):
         log(f"  trace {membrane} at N_x={args.ma_trace_nx}: phi_M {traces[membrane]['min_mV']}.."
             f"{traces[membrane]['max_mV']} mV")
     hist = {str(int(k)): int(v) for k, v in zip(*np.unique(its[1:], return_counts=True))}
+    p_n = None
+    if args.ma_pn_steps > 0:
+        # the time-dependent P_n: the hierarchy rebuilt from every step's matrix
+        m = min(args.ma_pn_steps, n_steps)
+        case_n = model_a_evolution_case(nx=nx, membrane="hh", n_steps=m)
+        sn = KnpSolver(case_n, amg=amg_opts(precision=1, operator_step=1),
+                       solve=solve_opts(rtol=1e-6, restart=30, max_it=2000))
+        its_n, t_n = [], []
+        for n in range(1, m + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = sn.step()
+            torch.cuda.synchronize()
+            t_n.append(time.perf_counter() - t0)
+            its_n.append(info.its)
+        p_n = {"steps": m, "its_per_step_P_n": its_n, "its_per_step_P_0": [int(k) for k in its[:m]],
+               "mean_its_P_n": round(float(np.mean(its_n)), 3), "mean_its_P_0": round(float(np.mean(its[:m])), 3),
+               "ms_per_step_P_n_steps_2_on": round(1e3 * float(np.mean(t_n[1:])), 2),
+               "ms_per_step_P_0_steps_2_on": round(1e3 * float(times[:m - 1].mean()), 3)}
+        log(f"  P_n over {m} steps: mean its {p_n['mean_its_P_n']} vs P_0 {p_n['mean_its_P_0']}, "
+            f"{p_n['ms_per_step_P_n_steps_2_on']} ms/step with the rebuild")
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle.assemble import Assembler, initial_gates, initial_state
+        from oracle.timeloop import step as oracle_step
+        oc = model_a_evolution_case(nx=args.ma_cpu_nx, membrane="hh", n_steps=args.ma_cpu_steps)
+        asm = Assembler(oc)
+        u, w = initial_state(oc, asm.lay), initial_gates(oc, asm.lay)
+        ts = []
+        for n in range(1, args.ma_cpu_steps + 1):
+            t0 = time.perf_counter()
+            u, w, _ = oracle_step(asm, u, w, n, oc.dt)
+            ts.append(time.perf_counter() - t0)
+            log(f"  oracle step {n}: {ts[-1]:.2f} s (N={asm.lay.N})")
+        per = float(np.median(ts))
+        cpu = {"value": round(1.0 / per, 4), "unit": "time steps/s", "cores": 1, "kind": "oracle",
+               "sample": f"{args.ma_cpu_steps} oracle steps (assembly + SuperLU) of the same Model A case at "
+                         f"N_x={args.ma_cpu_nx}, N={asm.lay.N} unknowns; median s/step {per:.2f}"}
     out = {
         "metric": "Model A time evolution: time steps/s and GMRES iterations per step over 300 steps",
         "value": round(len(times) / times.sum(), 3),
@@ -284,10 +322,11 @@ def model_a_bench(args, log):
         "paper_its_per_step": "1-6 (LU(P_0) and AMG(P_0), 32 MPI processes, its own stopping rule)",
         "phi_M_spread_on_gamma_V": spread,
         "spikes": spikes,
+        "time_dependent_P_n": p_n,
         "traces_nx": args.ma_trace_nx,
         "traces": traces,
         "roofline": roof,
-        "cpu_baseline": None,
+        "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
 
@@ -514,7 +553,11 @@ def main():
                     help="Model A's time evolution (2D, N_x = 512, 300 steps) instead of the step throughput")
     ap.add_argument("--ma-nx", type=int, default=512)
     ap.add_argument("--ma-steps", type=int, default=300)
-    ap.add_argument("--ma-trace-nx", type=int, default=64)
+    ap.add_argument("--ma-trace-nx", type=int, default=64, help="0 skips the three membrane traces")
+    ap.add_argument("--ma-cpu-nx", type=int, default=256)
+    ap.add_argument("--ma-cpu-steps", type=int, default=3)
+    ap.add_argument("--ma-pn-steps", type=int, default=60,
+                    help="steps run again with the hierarchy rebuilt from every step's matrix (0 skips)")
     ap.add_argument("--fd-rtol-fwd", type=float, default=1e-11)
     ap.add_argument("--fd-rtol-adj", type=float, default=1e-8)
     args = ap.parse_args()

@@ -102,6 +102,9 @@ typedef struct {
     int32_t coarse_pre_degree;   /* coarser levels: pre-smoothing degree (>= 0;    */
                                  /* 0, here and above: restrict the right-hand side) */
     int32_t coarse_post_degree;  /* coarser levels: post-smoothing degree (>= 1)   */
+    int32_t operator_step;  /* 0: P_0, the diagonal blocks of the first assembled
+                               matrix, for every step (the paper's choice);
+                               1: P_n, those of the most recently assembled one  */
 } knp_amg_opts;
 
 typedef struct {
@@ -180,11 +183,13 @@ knp_status knp_assemble_step(knp_ctx *ctx, double t_n, double dt, const double *
                              double *gates, const double *theta, double *f_out);
 
 /* Build the algebraic-multigrid hierarchy of P_0 (eq. ``P_prec``), frozen for all
- * steps (same section).  Must follow the first knp_assemble_step (else
- * KNP_E_STATE).  opts NULL = defaults (FP64, strength 0.6, Chebyshev smoothing on
- * [lmax/2.5, lmax] of degree 0 before and 5 after the coarse correction on the
- * finest level and 0 and 1 on the coarser levels, coarse_max 2000, max_levels 20,
- * coarse_drop 0.01). */
+ * steps (same section), or with operator_step = 1 of the time-dependent P_n of the
+ * most recent knp_assemble_step (the alternative that section weighs against P_0;
+ * the caller calls again after each assembly).  Must follow the first
+ * knp_assemble_step (else KNP_E_STATE).  opts NULL = defaults (FP64, strength 0.6,
+ * Chebyshev smoothing on [lmax/2.5, lmax] of degree 0 before and 5 after the coarse
+ * correction on the finest level and 0 and 1 on the coarser levels, coarse_max
+ * 2000, max_levels 20, coarse_drop 0.01, operator_step 0). */
 knp_status knp_amg_setup(knp_ctx *ctx, const knp_amg_opts *opts);
 
 /* Shape of the hierarchy built by knp_amg_setup: number of levels (<= 32) and,

@@ -592,6 +592,26 @@ knp_status knp_set_params(knp_ctx *c, const knp_params *p) {
     });
 }
 
+// The diagonal blocks (one per region and field, eq. ``P_prec``) of the stored
+// matrix S A S, on the pattern of P_0, in the order the AMG setup reads them.
+static std::vector<double> diagonal_blocks(knp_ctx *c) {
+    const HostMesh &h = c->hm;
+    std::vector<double> vals(h.nnz), out(h.nnz_p0);
+    c->d_vals.download(vals.data(), h.nnz, c->stream);
+    int64_t o = 0;
+    for (int r = 0; r < 2; ++r)
+        for (int f = 0; f < 4; ++f)
+            for (int64_t j = 0; j < h.Nr[r]; ++j) {
+                const int64_t row = h.off[r] + f * h.Nr[r] + j;
+                const int64_t n = h.prow[r][j + 1] - h.prow[r][j];
+                const int64_t len = h.rowptr[row + 1] - h.rowptr[row];
+                const int64_t g = len - (f < 3 ? 2 : 4) * n;
+                const int64_t seg = c->rstart[row] + (r == 0 ? 0 : g) + (f < 3 ? 0 : 3 * n);
+                for (int64_t q = 0; q < n; ++q) out[o++] = vals[seg + q];
+            }
+    return out;
+}
+
 knp_status knp_assemble_step(knp_ctx *c, double t_n, double dt, const double *u_prev, double *gates,
                              const double *theta, double *f_out) {
     return guarded(c, [&]() -> knp_status {
@@ -644,21 +664,9 @@ knp_status knp_assemble_step(knp_ctx *c, double t_n, double dt, const double *u_
             launch::scaling_from_diag(h.N, c->d_vals.p, c->d_diag.p, c->d_sc.p, s);
             matrix_and_rhs(true);
             // P_0: the diagonal blocks of the first (scaled) matrix, kept on the host for AMG setup
-            std::vector<double> vals(h.nnz), sc(h.N);
-            c->d_vals.download(vals.data(), h.nnz, s);
+            std::vector<double> sc(h.N);
+            c->p0_vals = diagonal_blocks(c);
             c->d_sc.download(sc.data(), h.N, s);
-            c->p0_vals.resize(h.nnz_p0);
-            int64_t o = 0;
-            for (int r = 0; r < 2; ++r)
-                for (int f = 0; f < 4; ++f)
-                    for (int64_t j = 0; j < h.Nr[r]; ++j) {
-                        const int64_t row = h.off[r] + f * h.Nr[r] + j;
-                        const int64_t n = h.prow[r][j + 1] - h.prow[r][j];
-                        const int64_t len = h.rowptr[row + 1] - h.rowptr[row];
-                        const int64_t g = len - (f < 3 ? 2 : 4) * n;
-                        const int64_t seg = c->rstart[row] + (r == 0 ? 0 : g) + (f < 3 ? 0 : 3 * n);
-                        for (int64_t q = 0; q < n; ++q) c->p0_vals[o++] = vals[seg + q];
-                    }
             c->near_null.resize(h.N);
             for (int64_t i = 0; i < h.N; ++i) c->near_null[i] = 1.0 / sc[i];
             c->dt_first = dt;
@@ -679,15 +687,19 @@ knp_status knp_amg_setup(knp_ctx *c, const knp_amg_opts *opts) {
     return guarded(c, [&]() -> knp_status {
         need_device(c);
         if (!c->assembled) return fail(c, KNP_E_STATE, "knp_assemble_step must come first");
-        knp_amg_opts o{0, 0.6, 5, 2.5, 2000, 20, 0.01, 0, 0, 1};
+        knp_amg_opts o{0, 0.6, 5, 2.5, 2000, 20, 0.01, 0, 0, 1, 0};
         if (opts) o = *opts;
         if (o.precision != 0 && o.precision != 1) return fail(c, KNP_E_ARG, "precision must be 0 or 1");
         if (!(o.strength > 0.0 && o.strength < 1.0) || o.cheb_degree < 1 || !(o.cheb_ratio > 1.0) ||
             o.coarse_max < 1 || o.max_levels < 1 || !(o.coarse_drop >= 0.0 && o.coarse_drop < 1.0) ||
-            o.cheb_pre_degree < 0 || o.coarse_pre_degree < 0 || o.coarse_post_degree < 1)
+            o.cheb_pre_degree < 0 || o.coarse_pre_degree < 0 || o.coarse_post_degree < 1 ||
+            (o.operator_step != 0 && o.operator_step != 1))
             return fail(c, KNP_E_ARG, "invalid AMG options");
         hip_check(hipSetDevice(c->device), "set device");
-        amg_build(c->amg, c->hm, c->p0_vals, c->near_null, o, c->stream);
+        if (o.operator_step == 1)
+            amg_build(c->amg, c->hm, diagonal_blocks(c), c->near_null, o, c->stream);
+        else
+            amg_build(c->amg, c->hm, c->p0_vals, c->near_null, o, c->stream);
         c->m_alloc = -1;   // Z precision may change
         return KNP_OK;
     });

@@ -59,9 +59,11 @@ class KnpSolver:
         return (torch.as_tensor(ri, device=self.dev), torch.as_tensor(re, device=self.dev))
 
     def assemble(self, n=None):
+        """Assemble step n; the hierarchy is built after the first assembly, and rebuilt
+        after every one when the AMG options ask for the time-dependent P_n."""
         n = self.n + 1 if n is None else n
         self.ctx.assemble_step(n * self.case.dt, self.case.dt, self.u, self.gates, self.theta, self.f)
-        if not self.amg_ready:
+        if not self.amg_ready or self.amg_opts.operator_step == 1:
             self.ctx.amg_setup(self.amg_opts)
             self.amg_ready = True
 

@@ -19,6 +19,7 @@ from oracle import timeloop  # noqa: E402
 from oracle.assemble import Assembler, gamma_values, initial_gates, initial_state, p0_values  # noqa: E402
 from oracle.solve import gmres  # noqa: E402
 from oracle.timeloop import advance_gates  # noqa: E402
+from oracle.timeloop import step as oracle_step  # noqa: E402
 from paper_2403_04491_amd import KnpSolver, amg_opts, knp, solve_opts  # noqa: E402
 
 PARITY = dict(rtol=1e-12, restart=400, max_it=3000, reorth=1)
@@ -308,31 +309,61 @@ def test_time_steps_match_oracle(name, steps, precision, tol):
 def test_model_a_evolution_matches_oracle():
     """Model A's time evolution (HH, stimulus every 10 ms, uniform initial data) over
     300 steps at N_x = 32, three action potentials: every 10th state against the
-    oracle's, and the membrane potential at every step."""
+    oracle's trajectory and against one oracle step from the GPU's own previous state,
+    and the membrane potential at every step."""
     case = model_a_evolution_case(nx=32, n_steps=300)
     print(f"[evolution] {case.name} steps=300", flush=True)
     ref = timeloop.run(case)
-    lay = ref["asm"].lay
+    asm = ref["asm"]
+    lay = asm.lay
     s = KnpSolver(case, amg=amg_opts(precision=0), solve=solve_opts(**PARITY))
     ri, re = s.membrane_rows()
     order = np.argsort(s.gamma)
     assert np.array_equal(s.gamma[order], np.sort(lay.gamma))
-    worst, worst_phiM, its = 0.0, 0.0, []
+    worst, worst_step, worst_phiM, its = 0.0, 0.0, 0.0, []
     for n in range(1, 301):
+        u_prev, w_prev = s.u.cpu().numpy(), s.gates.cpu().numpy()
         its.append(s.step().its)
         phiM = (s.u[ri] - s.u[re]).cpu().numpy()
         _, _, ref_phiM = gamma_values(lay, ref["u"][n])
         worst_phiM = max(worst_phiM, float(np.abs(phiM[order] - ref_phiM[np.argsort(lay.gamma)]).max()))
-        if n % 10 == 0:
-            e = block_err(s.info, s.u.cpu().numpy(), ref["u"][n])
-            worst = max(worst, max(e.values()))
+        if n % 10 == 0 or n <= 20:
+            u = s.u.cpu().numpy()
+            worst = max(worst, max(block_err(s.info, u, ref["u"][n]).values()))
+            one, _, _ = oracle_step(asm, u_prev, w_prev, n, case.dt)
+            worst_step = max(worst_step, max(block_err(s.info, u, one).values()))
     print(f"  iterations min/mean/max {min(its)}/{np.mean(its):.1f}/{max(its)}, worst block error "
-          f"{worst:.2e}, worst phi_M error {worst_phiM:.2e} V", flush=True)
-    # each step's solution carries up to ~2e-10 relative error in the potentials on both
-    # sides (the rounding floor of LU on a system with cond > 1e10); over 300 steps these
-    # add up to at most 300 x 2e-10 = 6e-8
-    assert worst <= 300 * 2e-10
+          f"{worst:.2e} (one step from the same state {worst_step:.2e}), worst phi_M error "
+          f"{worst_phiM:.2e} V", flush=True)
+    assert worst_step <= 1e-8
+    # the time map amplifies perturbations during an action potential (explicit membrane
+    # current with dt g / C_m > 2 at the peak): a relative change of 1e-10 in u_0, the
+    # rounding level of one solve, moves the oracle's own potentials by up to 3.8e-8
+    # over these 300 steps, so the two trajectories are held to 6e-8
+    assert worst <= 6e-8
     assert worst_phiM <= 1e-8 * 0.1          # 1e-8 of the 0.1 V scale of an action potential
+
+
+def test_time_dependent_p_n_matches_oracle():
+    """The hierarchy of P_n, rebuilt from each step's matrix (operator_step = 1),
+    preconditions every step to the oracle's solution; through the first action
+    potential its iteration counts stay near those of the frozen P_0, which the paper
+    finds makes little or no difference."""
+    case = model_a_evolution_case(nx=32, n_steps=12)
+    print(f"[P_n] {case.name} steps=12", flush=True)
+    asm = Assembler(case)
+    its = {}
+    for op in (0, 1):
+        s = KnpSolver(case, amg=amg_opts(operator_step=op), solve=solve_opts(**PARITY))
+        its[op] = []
+        for n in range(1, 13):
+            u_prev, w_prev = s.u.cpu().numpy(), s.gates.cpu().numpy()
+            its[op].append(s.step().its)
+            one, _, _ = oracle_step(asm, u_prev, w_prev, n, case.dt)   # one step, same state
+            e = block_err(s.info, s.u.cpu().numpy(), one)
+            assert max(e.values()) <= 1e-8, (op, n, e)
+    print(f"  iterations P_0 {its[0]}, P_n {its[1]}", flush=True)
+    assert sum(its[1]) <= 1.5 * sum(its[0])
 
 
 def test_paper_tolerance_iterations_and_error():
@@ -406,6 +437,9 @@ def test_error_paths():
     assert ok and info.its == 0 and float(y.abs().max()) == 0.0
     with pytest.raises(knp.KnpError) as ei:
         s.ctx.amg_setup(amg_opts(precision=3))
+    assert ei.value.status == 1
+    with pytest.raises(knp.KnpError) as ei:
+        s.ctx.amg_setup(amg_opts(operator_step=2))
     assert ei.value.status == 1
     # membrane models: unknown codes and invalid Kir-Na/K parameters are argument errors;
     # cells of other models ignore the pump parameters
