@@ -298,11 +298,17 @@ def test_time_steps_match_oracle(name, steps, precision, tol):
     case = ASM_CASES[name]()
     print(f"[steps] {name} steps={steps} precision={precision}", flush=True)
     s, gpu, ref, its = run_both(case, steps, precision)
-    worst = 0.0
+    worst = worst_inc = 0.0
     for n in range(1, steps + 1):
         e = block_err(s.info, gpu[n], ref[n])
         worst = max(worst, max(e.values()))
-    print(f"  its per step {its}, worst block error {worst:.2e}", flush=True)
+        # the step's increment, a stricter diagnostic (concentrations change little per step)
+        for b in blocks(s.info).values():
+            d_ref = ref[n][b] - ref[n - 1][b]
+            worst_inc = max(worst_inc, float(np.linalg.norm((gpu[n][b] - gpu[n - 1][b]) - d_ref)
+                                             / np.linalg.norm(d_ref)))
+    print(f"  its per step {its}, worst block error {worst:.2e}, worst increment error {worst_inc:.2e}",
+          flush=True)
     assert worst <= tol
 
 
