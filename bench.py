@@ -569,8 +569,8 @@ def main():
     if args.warmup < 1:
         ap.error("--warmup must be >= 1 (the first step includes the AMG setup)")
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1 "
-                                   "(the multi-GPU sharding is a design, not a code path)"}))
+        print(json.dumps({"error": "the benchmark runs on exactly one GPU; --gpus must be 1 "
+                                   "(sharding across GPUs is described in the design notes, not implemented)"}))
         sys.exit(2)
     if args.adjoint:
         adjoint_bench(args, log)
