@@ -74,11 +74,14 @@ def _moment(m, idx):
 # --------------------------------------------------------------------------- bulk
 def bulk_coo(case, lay: Layout, r: int, weight=None, kind="stiff"):
     """COO triplets (rows, cols, vals) of M_r ("mass"), A_r ("stiff") or the
-    weighted stiffness int weight grad(phi_j).grad(phi_l) with a P1 weight given
-    by region-local nodal values (exact: mean over the element times A_T)."""
+    weighted stiffness int weight grad(phi_j).grad(phi_l) with a weight in the same
+    space given by region-local nodal values (P1: exact as the mean over the element
+    times A_T; P2: exact barycentric moments)."""
     sel = (case.tag >= 1) if r == 0 else (case.tag == 0)
     el_glob = case.elem[sel].astype(np.int64)
     el = lay.loc[r][el_glob]
+    if getattr(case, "degree", 1) == 2:
+        return _bulk_coo_p2(case, el_glob, el, weight, kind)
     vol, g = simplex_geometry(case.xyz, el_glob)
     d1 = el.shape[1]
     rows, cols, vals = [], [], []
@@ -96,10 +99,39 @@ def bulk_coo(case, lay: Layout, r: int, weight=None, kind="stiff"):
     return np.concatenate(rows), np.concatenate(cols), np.concatenate(vals)
 
 
+def _bulk_coo_p2(case, el_glob, el, weight, kind):
+    from .p2 import reference_tensors
+    d = case.dim
+    M, S, W = reference_tensors(d)
+    vol, g = simplex_geometry(case.xyz, el_glob[:, :d + 1])
+    G = np.einsum("eid,ejd->eij", g, g)              # grad(lambda_i) . grad(lambda_j)
+    if kind == "mass":
+        local = vol[:, None, None] * M[None]
+    elif weight is None:
+        local = vol[:, None, None] * np.einsum("eij,abij->eab", G, S)
+    else:
+        local = vol[:, None, None] * np.einsum("em,eij,mabij->eab", weight[el], G, W)
+    n = el.shape[1]
+    rows = np.repeat(el, n, axis=1).ravel()
+    cols = np.tile(el, (1, n)).ravel()
+    return rows, cols, local.reshape(len(el), n * n).ravel()
+
+
 def gamma_coo(case, lay: Layout, weight=None):
-    """COO over global vertex ids of int_Gamma w phi_a phi_b (w = 1 if None; else a
-    P1 membrane field given by nodal values indexed by global vertex id)."""
+    """COO over global node ids of int_Gamma w phi_a phi_b (w = 1 if None; else a
+    membrane field in the same space given by nodal values indexed by global id)."""
     f = lay.facets
+    if getattr(case, "degree", 1) == 2:
+        from .p2 import facet_tensors
+        m = case.dim - 1
+        meas = facet_measure(case.xyz, f[:, :m + 1])
+        F2, F3 = facet_tensors(m)
+        n = f.shape[1]
+        if weight is None:
+            local = meas[:, None, None] * F2[None]
+        else:
+            local = meas[:, None, None] * np.einsum("ec,abc->eab", weight[f], F3)
+        return np.repeat(f, n, axis=1).ravel(), np.tile(f, (1, n)).ravel(), local.reshape(len(f), n * n).ravel()
     meas = facet_measure(case.xyz, f)
     m = f.shape[1] - 1
     rows, cols, vals = [], [], []

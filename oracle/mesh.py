@@ -24,7 +24,8 @@ class Layout:
     verts: tuple            # (V_i, V_e): sorted global vertex ids per region
     loc: np.ndarray         # int64 [2, n_vert]; region-local index or -1
     gamma: np.ndarray       # sorted global ids of membrane vertices
-    facets: np.ndarray      # int64 [n_f, dim]; membrane facets (sorted vertex ids)
+    facets: np.ndarray      # int64 [n_f, dim]; membrane facets (sorted vertex ids; for P2
+                            # then the facet's edge nodes)
     facet_cell: np.ndarray  # int64 [n_f]; cell id (>= 1) of the ICS side
     vert_cell: np.ndarray   # int64 [n_vert]; cell id of ICS vertices, 0 otherwise
     pin_vertex: int
@@ -81,7 +82,8 @@ def build_layout(case) -> Layout:
     if np.any((vert_cell > 0) & (lo != vert_cell)):
         raise ValueError("two cells share a vertex")
 
-    faces, owner = element_faces(elem)
+    elem_v = getattr(case, "elem_vertices", elem)      # P2: the vertex columns
+    faces, owner = element_faces(elem_v)
     key_order = np.lexsort(faces.T[::-1])
     faces = faces[key_order]
     owner = owner[key_order]
@@ -93,6 +95,9 @@ def build_layout(case) -> Layout:
     if np.any((t1 != t2) & (t1 > 0) & (t2 > 0)):
         raise ValueError("two cells share a facet")
     facets = faces[first[is_gamma]]
+    if getattr(case, "degree", 1) == 2:
+        from .p2 import facet_nodes
+        facets = facet_nodes(case, facets)
     facet_cell = np.maximum(t1[is_gamma], t2[is_gamma])
     # boundary faces (appearing once) must be extracellular
     count_two = np.zeros(len(faces), dtype=bool)

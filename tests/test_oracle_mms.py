@@ -25,6 +25,7 @@ import pytest
 
 from knp_inputs import model_a_case
 from oracle.assemble import Assembler, initial_gates
+from oracle.p2 import p2_case
 from oracle.mesh import PHI
 from oracle.solve import lu_solve
 
@@ -67,8 +68,10 @@ class FlatPoly:
         return sum(self._prod(x, [2 if e == d else 0 for e in range(n)]) for d in range(n))
 
 
-def _solve_mms(dim, nx, dt=1e-4):
+def _solve_mms(dim, nx, dt=1e-4, degree=1):
     case = model_a_case(dim, nx, "leak", dt, 1)
+    if degree == 2:
+        case = p2_case(case)
     p = case.params
     L = 1e-6
     z = np.array(p["z"])
@@ -169,3 +172,20 @@ def test_mms_second_order(dim, sizes):
     rates = np.log2(errs[-2] / errs[-1]) / np.log2(sizes[-1] / sizes[-2])
     assert np.all(rates > 1.8), rates
     assert np.all(rates < 2.6), rates
+
+
+def test_mms_p2_third_order_2d():
+    """Quadratic elements (p = 2, Sec. "Spatial discretization"): the nodal error of
+    every field converges at least at third order in L2 (2D, N_x = 16 -> 32)."""
+    errs = []
+    for nx in (16, 32):
+        case, lay, u, us = _solve_mms(2, nx, degree=2)
+        row = []
+        for r in (0, 1):
+            idx = np.arange(lay.N_r[r])
+            for f in range(4):
+                d = lay.dof(r, f, idx)
+                row.append(_l2(case, lay, r, u[d] - us[d]))
+        errs.append(np.array(row))
+    rates = np.log2(errs[0] / errs[1])
+    assert np.all(rates > 2.7), rates

@@ -6,6 +6,7 @@ enumerations, algebraic identities the discrete system must satisfy, closed-form
 special cases, and paper-printed values.
 """
 import itertools
+import math
 
 import numpy as np
 import pytest
@@ -19,6 +20,7 @@ from oracle.assemble import (Assembler, bulk_coo, gamma_coo, gamma_values, hh_ra
                              initial_gates, initial_state, kir_factor, membrane_terms,
                              pump_flux, rush_larsen, p0_values, stimulus)
 from oracle.mesh import build_layout, structural_pattern
+from oracle.p2 import p2_case
 from oracle.solve import dense_solve, gmres, lu_solve
 
 
@@ -42,6 +44,22 @@ def test_dof_formula_small(d, nx):
     assert lay.N == dof_formula(nx, d)
     # duplicated membrane vertices: N_i + N_e - n_vert = |Gamma vertices|
     assert sum(lay.N_r) - lay.n_vert == len(lay.gamma)
+
+
+@pytest.mark.parametrize("d,nx", [(2, 4), (2, 8), (2, 16), (3, 4), (3, 8)])
+def test_dof_formula_p2(d, nx):
+    """The DOF-count formula of Sec. "Model A" for p = 2: vertex and edge nodes, the
+    membrane ones duplicated."""
+    lay = build_layout(p2_case(model_a_case(d, nx)))
+    assert lay.N == dof_formula(nx, d, p=2)
+    assert sum(lay.N_r) - lay.n_vert == len(lay.gamma)
+
+
+def test_dof_count_p2_at_the_largest_robustness_case():
+    """Sec. "Iterative solver robustness" prints N = 4.2e6 for (N_x, p) = (512, 2)."""
+    lay = build_layout(p2_case(model_a_case(2, 512)))
+    assert lay.N == dof_formula(512, 2, p=2) == 4210692
+    assert round(lay.N / 1e5) == 42
 
 
 def _brute_pattern(case):
@@ -126,12 +144,24 @@ def run3d():
 
 
 @pytest.fixture(scope="module")
+def run2d_p2():
+    case = p2_case(model_a_case(2, 8, "hh", 1e-4, 2, stim=True))
+    return case, timeloop.run(case, n_steps=2, keep_systems=True)
+
+
+@pytest.fixture(scope="module")
+def run3d_p2():
+    case = p2_case(model_a_case(3, 4, "hh", 5e-5, 2, cfg_id=2))
+    return case, timeloop.run(case, n_steps=2, keep_systems=True)
+
+
+@pytest.fixture(scope="module")
 def run3d_kir():
     case = model_a_case(3, 8, "kir", 5e-5, 2, cfg_id=2)
     return case, timeloop.run(case, n_steps=2, keep_systems=True)
 
 
-@pytest.mark.parametrize("which", ["run2d", "run3d", "run3d_kir"])
+@pytest.mark.parametrize("which", ["run2d", "run3d", "run3d_kir", "run2d_p2", "run3d_p2"])
 def test_nullspace_unpinned(which, request):
     """The unpinned operator annihilates e = (0, 1_i, 0, 1_e) from both sides and the
     potential rows of f sum to zero (Remark on the constant-potential nullspace)."""
@@ -160,7 +190,7 @@ def _gmass(case, lay, weight=None):
     return sp.coo_matrix((gv, (gr, gc)), shape=(lay.n_vert,) * 2).tocsr()
 
 
-@pytest.mark.parametrize("which", ["run2d", "run3d", "run3d_kir"])
+@pytest.mark.parametrize("which", ["run2d", "run3d", "run3d_kir", "run2d_p2", "run3d_p2"])
 def test_invariants(which, request):
     """I1: sum_k z_k c_k is unchanged at every node (electroneutrality, eq. ``knp``).
     I2: per cell, C_m int (phi_M^n - phi_M^{n-1}) = -dt int I_ch (test w = 1 on the
@@ -319,6 +349,24 @@ def test_lu_p0_gmres_iteration_count(row):
     assert 3 <= info["its"] <= 4 and (printed == 3 or info["its"] == printed), info["its"]
     _, info0 = gmres(A, s.f, x0=u0, restart=30, rtol=1e-6, maxiter=300)
     assert info0["its"] >= 100          # unpreconditioned GMRES stalls (same section)
+
+
+@pytest.mark.parametrize("row", golden("lu_p0_iterations.txt"))
+def test_lu_p0_gmres_iteration_count_p2(row):
+    """The same 3-4 iterations with quadratic elements, which the same section states
+    for p in {1, 2} (N_x = 16, N = 4,612)."""
+    dt, printed = float(row[0]), int(row[1])
+    case = p2_case(model_a_case(2, 16, "hh", dt, 1, noise=0.0))
+    asm = Assembler(case)
+    lay = asm.lay
+    u0 = initial_state(case, lay)
+    s = asm.assemble(u0, initial_gates(case, lay), dt, dt)
+    A = s.csr()
+    P0 = sp.csr_matrix((p0_values(s, lay), s.colidx, s.rowptr), shape=A.shape)
+    lu = spla.splu(sp.csc_matrix(P0))
+    _, info = gmres(lambda v: lu.solve(A @ v), lu.solve(s.f), x0=u0, restart=30,
+                    rtol=1e-6, maxiter=100)
+    assert 3 <= info["its"] <= 4 and (printed == 3 or info["its"] == printed), info["its"]
 
 
 # --------------------------------------------------------------------------- Kir-Na/K
@@ -504,3 +552,82 @@ def test_model_a_p_n_and_p_0_need_the_same_iterations(model_a_run):
         its = [gmres(lambda v, lu=lu: lu.solve(A @ v), lu.solve(s.f), x0=res["u"][n - 1], restart=30,
                      rtol=1e-6, maxiter=100)[1]["its"] for lu in (lu0, lun)]
         assert abs(its[0] - its[1]) <= 1, (n, its)
+
+
+def _duffy_rule(d, n=8):
+    """Points (barycentric) and weights (per unit measure) of a collapsed Gauss-Legendre
+    rule on the d-simplex, exact for polynomials of degree < 2n - d."""
+    g, w = np.polynomial.legendre.leggauss(n)
+    g, w = 0.5 * (g + 1.0), 0.5 * w
+    pts, wts = [], []
+    for idx in itertools.product(range(n), repeat=d):
+        u = [g[i] for i in idx]
+        wt = np.prod([w[i] for i in idx])
+        # x_1 = u_1, x_2 = (1 - u_1) u_2, ...; Jacobian prod (1 - u_k)^(d - k)
+        x, rest = [], 1.0
+        for k in range(d):
+            x.append(rest * u[k])
+            wt *= (1.0 - u[k]) ** (d - 1 - k)
+            rest *= 1.0 - u[k]
+        lam = [1.0 - sum(x)] + x
+        pts.append(lam)
+        wts.append(wt * math.factorial(d))        # the reference simplex has measure 1/d!
+    return np.array(pts), np.array(wts)
+
+
+def _p2_values_and_lambda_derivs(lam):
+    """P2 basis by its closed forms (vertex lambda_a(2 lambda_a - 1), edge 4 lambda_a
+    lambda_b) and its derivatives in each lambda_i, at one barycentric point."""
+    n = len(lam)
+    pairs = list(itertools.combinations(range(n), 2))
+    val = [lam[a] * (2 * lam[a] - 1) for a in range(n)] + [4 * lam[a] * lam[b] for a, b in pairs]
+    der = np.zeros((n + len(pairs), n))
+    for a in range(n):
+        der[a, a] = 4 * lam[a] - 1
+    for q, (a, b) in enumerate(pairs):
+        der[n + q, a] = 4 * lam[b]
+        der[n + q, b] = 4 * lam[a]
+    return np.array(val), der
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_p2_element_integrals_against_quadrature(d):
+    """The exact barycentric moments of the P2 mass, stiffness and weighted stiffness
+    on one random simplex equal a collapsed Gauss-Legendre quadrature of the basis
+    written out in closed form (Sec. "Spatial discretization", p = 2)."""
+    from oracle.assemble import simplex_geometry
+    from oracle.p2 import reference_tensors
+    rng = np.random.default_rng(d)
+    x = rng.standard_normal((d + 1, d))
+    vol, g = simplex_geometry(x, np.arange(d + 1)[None, :])
+    vol, g = vol[0], g[0]
+    M, S, W = reference_tensors(d)
+    G = g @ g.T
+    w = rng.uniform(0.5, 2.0, M.shape[0])
+    pts, wts = _duffy_rule(d)
+    assert abs(wts.sum() - 1.0) < 1e-13
+    Mq = np.zeros_like(M)
+    Kq = np.zeros_like(M)
+    Wq = np.zeros_like(M)
+    for lam, wt in zip(pts, wts):
+        val, der = _p2_values_and_lambda_derivs(lam)
+        grad = der @ g                                # physical gradients
+        Mq += wt * np.outer(val, val)
+        Kq += wt * grad @ grad.T
+        Wq += wt * (w @ val) * grad @ grad.T
+    assert np.abs(M - Mq).max() < 1e-13
+    assert np.abs(np.einsum("ij,abij->ab", G, S) - Kq).max() < 1e-11 * np.abs(Kq).max()
+    assert np.abs(np.einsum("m,ij,mabij->ab", w, G, W) - Wq).max() < 1e-11 * np.abs(Wq).max()
+    assert vol > 0
+
+
+def test_p2_initial_data_interpolates_linear_fields():
+    """Initial data at the edge nodes is the mean of the two vertices' values: exact
+    for data linear in the coordinates (the P1 interpolant of the per-vertex data)."""
+    case = model_a_case(3, 4)
+    lin = 10.0 + 1e6 * case.xyz @ np.array([1.0, 2.0, -3.0])
+    case.conc0[:] = lin[None, None, :]
+    c2 = p2_case(case)
+    expect = 10.0 + 1e6 * c2.xyz @ np.array([1.0, 2.0, -3.0])
+    assert np.allclose(c2.conc0[0, 1], expect, rtol=1e-14, atol=1e-12)
+    assert c2.xyz.shape[0] == case.n_vert + len(c2.edges)
