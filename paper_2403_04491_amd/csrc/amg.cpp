@@ -270,6 +270,7 @@ int64_t aggregate(int64_t n, const std::vector<int64_t> &srow, const std::vector
 struct HostLevel {
     Csr A, P, R;
     double lmax;
+    std::vector<int8_t> blk;   // (region, field) block of each row: 4 r + f
 };
 
 void invert_dense(int n, std::vector<double> &a) {   // Gauss-Jordan, partial pivoting, in place
@@ -420,6 +421,7 @@ void amg_build(Amg &amg, const HostMesh &m, const std::vector<double> &p0_vals, 
     amg.coarse_pre = std::max(0, o.coarse_pre_degree);
     amg.coarse_post = std::max(1, o.coarse_post_degree);
     amg.ratio = o.cheb_ratio;
+    amg.field_split = o.field_split == 1;
     // P_0 in CSR, in the solver's order (DOF off_r + 4 j + f): per region the scalar
     // pattern of the region for each field.  p0_vals and near_null come in ABI order
     // (block by block: region r, field f, then the pattern row by row).
@@ -452,6 +454,9 @@ void amg_build(Amg &amg, const HostMesh &m, const std::vector<double> &p0_vals, 
     }
 
     std::vector<HostLevel> H;
+    // block of each row, carried to the coarser levels (aggregates never leave a block)
+    std::vector<int8_t> RB(m.N);
+    for (int64_t i = 0; i < m.N; ++i) RB[i] = int8_t((i >= m.off[1] ? 4 : 0) + (i & 3));
     const int max_levels = std::max(1, o.max_levels);
     const int64_t coarse_max = std::max<int32_t>(1, o.coarse_max);
     while (true) {
@@ -459,6 +464,7 @@ void amg_build(Amg &amg, const HostMesh &m, const std::vector<double> &p0_vals, 
         L.A = std::move(A);
         const int64_t n = L.A.nrows;
         if (n <= coarse_max || int(H.size()) + 1 >= max_levels) {
+            L.blk = RB;
             H.push_back(std::move(L));
             break;
         }
@@ -468,6 +474,7 @@ void amg_build(Amg &amg, const HostMesh &m, const std::vector<double> &p0_vals, 
         std::vector<int32_t> agg;
         const int64_t nc = aggregate(n, srow, scol, agg);
         if (double(nc) > 0.85 * double(n)) {   // coarsening stalled: make this the coarsest
+            L.blk = RB;
             H.push_back(std::move(L));
             break;
         }
@@ -588,6 +595,12 @@ void amg_build(Amg &amg, const HostMesh &m, const std::vector<double> &p0_vals, 
         for (int64_t c = 0; c < nc; ++c) Bc[c] = bn[c] / dc[c];
         L.P = std::move(P);
         L.R = std::move(R);
+        {
+            std::vector<int8_t> RBc(nc, 0);
+            for (int64_t i = 0; i < n; ++i) RBc[agg[i]] = RB[i];
+            L.blk.swap(RB);
+            RB.swap(RBc);
+        }
         H.push_back(std::move(L));
         A = std::move(Ac);
         B.swap(Bc);
@@ -687,6 +700,28 @@ void amg_build(Amg &amg, const HostMesh &m, const std::vector<double> &p0_vals, 
                 }
             } else {
                 L->A.upload(H[l].A, f32, s);
+                // field split: block row ranges (contiguous on the coarser levels, since
+                // level 1 numbers its aggregates block by block and aggregation keeps the
+                // order) and a Gershgorin bound per block
+                const std::vector<int8_t> &rb = H[l].blk;
+                const int64_t nl = H[l].A.nrows;
+                bool ok = int64_t(rb.size()) == nl && nl < (int64_t(1) << 31);
+                for (int64_t i = 1; ok && i < nl; ++i) ok = rb[i] >= rb[i - 1];
+                if (ok) {
+                    L->nblocks = CHEB_BLOCKS;
+                    for (int q = 0; q <= CHEB_BLOCKS; ++q)
+                        L->bstart[q] = int32_t(std::lower_bound(rb.begin(), rb.end(), int8_t(q)) - rb.begin());
+                    for (int q = 0; q < CHEB_BLOCKS; ++q) {
+                        double g = 0.0;
+                        for (int64_t i = L->bstart[q]; i < L->bstart[q + 1]; ++i) {
+                            double sabs = 0.0;
+                            for (int64_t k = H[l].A.rowptr[i]; k < H[l].A.rowptr[i + 1]; ++k)
+                                sabs += std::fabs(H[l].A.val[k]);
+                            g = std::max(g, sabs);
+                        }
+                        L->blmax[q] = g > 0.0 ? g : H[l].lmax;
+                    }
+                }
             }
             L->P.upload(H[l].P, f32, s);
             L->R.upload(H[l].R, f32, s);
@@ -823,6 +858,24 @@ T *vcycle_level(Amg &amg, size_t l, const T *b, hipStream_t s, Timers *tm, T *ou
     std::vector<std::pair<double, double>> cpre, cc;
     if (dpre > 0) cheb_coeffs(L->lmax, amg.ratio, dpre, cpre);
     cheb_coeffs(L->lmax, amg.ratio, dpost, cc);
+    // field split: the same recurrences on each block's own interval
+    const bool fs = amg.field_split && l > 0 && L->nblocks == CHEB_BLOCKS;
+    std::vector<std::pair<double, double>> bpre[CHEB_BLOCKS], bcc[CHEB_BLOCKS];
+    if (fs)
+        for (int q = 0; q < CHEB_BLOCKS; ++q) {
+            if (dpre > 0) cheb_coeffs(L->blmax[q], amg.ratio, dpre, bpre[q]);
+            cheb_coeffs(L->blmax[q], amg.ratio, dpost, bcc[q]);
+        }
+    auto blocks_at = [&](const std::vector<std::pair<double, double>> (&tab)[CHEB_BLOCKS], size_t k) {
+        launch::ChebBlocks cb{};
+        cb.nb = CHEB_BLOCKS;
+        for (int q = 0; q <= CHEB_BLOCKS; ++q) cb.start[q] = L->bstart[q];
+        for (int q = 0; q < CHEB_BLOCKS; ++q) {
+            cb.c1[q] = tab[q][k].first;
+            cb.c2[q] = tab[q][k].second;
+        }
+        return cb;
+    };
     const int64_t n = L->n;
     const bool fbl = l == 0;     // level 0 is P_0 in the field-block layout
     const T *av = fbl ? LV<T>::FB(L) : LV<T>::A(L);
@@ -843,11 +896,13 @@ T *vcycle_level(Amg &amg, size_t l, const T *b, hipStream_t s, Timers *tm, T *ou
     Timers *t0 = (l == 0) ? tm : nullptr;
     // the finest level's timer class holds the steps that apply the operator (the
     // first step from x = 0 is a plain vector update)
-    auto cheb = [&](T *xout, double c1, double c2) {
+    auto cheb = [&](T *xout, double c1, double c2, const launch::ChebBlocks *cbk = nullptr) {
         Timers *tc = cur ? t0 : nullptr;
         hipEvent_t e = tc ? tc->begin(KNP_TIMER_CHEB_L0, s) : nullptr;
         if (fbl)
             launch::fb_cheb_step<T>(L->fb.view(), av, cur, b, prev, xout, c1, c2, s);
+        else if (cbk)
+            launch::cheb_step_blocks<T>(L->A.view(), av, cur, b, prev, xout, *cbk, s);
         else
             launch::cheb_step<T>(L->A.view(), av, cur, b, prev, xout, c1, c2, s);
         // b, x_k (gathered and own rows), x_{k-1} when c1 != 0, x_{k+1}
@@ -859,7 +914,10 @@ T *vcycle_level(Amg &amg, size_t l, const T *b, hipStream_t s, Timers *tm, T *ou
     T *bc = LV<T>::b(Lc);
     if (dpre > 0) {
         // pre-smoothing from x = 0, residual, restriction
-        for (size_t k = 0; k < cpre.size(); ++k) cheb(spare(), cpre[k].first, cpre[k].second);
+        for (size_t k = 0; k < cpre.size(); ++k) {
+            const launch::ChebBlocks cb = fs ? blocks_at(bpre, k) : launch::ChebBlocks{};
+            cheb(spare(), cpre[k].first, cpre[k].second, fs ? &cb : nullptr);
+        }
         hipEvent_t e = t0 ? t0->begin(KNP_TIMER_RESID_L0, s) : nullptr;
         if (fbl)
             launch::fb_residual<T>(L->fb.view(), av, cur, b, t, s);
@@ -887,7 +945,10 @@ T *vcycle_level(Amg &amg, size_t l, const T *b, hipStream_t s, Timers *tm, T *ou
     // post-smoothing, a recurrence of its own (its first step has c1 = 0); the last
     // step writes to `out` when given
     prev = nullptr;
-    for (size_t k = 0; k < cc.size(); ++k) cheb((out && k + 1 == cc.size()) ? out : spare(), cc[k].first, cc[k].second);
+    for (size_t k = 0; k < cc.size(); ++k) {
+        const launch::ChebBlocks cb = fs ? blocks_at(bcc, k) : launch::ChebBlocks{};
+        cheb((out && k + 1 == cc.size()) ? out : spare(), cc[k].first, cc[k].second, fs ? &cb : nullptr);
+    }
     return cur;
 }
 

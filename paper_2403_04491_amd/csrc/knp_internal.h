@@ -224,11 +224,19 @@ struct DevFieldBlock {
     }
 };
 
+// blocks of a field-split level: one per region and field
+constexpr int CHEB_BLOCKS = 8;
+
 struct Level {
     int64_t n = 0;
     double lmax = 2.0;           // spectral radius estimate of the (unit-diagonal) operator
     DevCsr A, P, R;              // P: n x n_coarse, R = P^T (A unused on level 0)
     DevFieldBlock fb;            // level 0 only: P_0 in the field-block layout
+    // field split (coarser levels): rows of block q (region r, field f: q = 4 r + f) are
+    // [bstart[q], bstart[q+1]); blmax[q] bounds that block's spectrum (Gershgorin)
+    int nblocks = 0;
+    int32_t bstart[CHEB_BLOCKS + 1] = {};
+    double blmax[CHEB_BLOCKS] = {};
     // level vectors (precision of the hierarchy); x, x2 and d are the three buffers the
     // Chebyshev recurrence in x rotates through, t the residual
     DArray<double> b64, x64, x2_64, t64, d64;
@@ -241,6 +249,7 @@ struct Amg {
     int degree = 3;                  // finest level: post-smoothing degree
     int pre_degree = 2;              // finest level: pre-smoothing degree
     int coarse_pre = 1, coarse_post = 1;   // coarser levels (pre 0: restrict b directly)
+    bool field_split = false;        // coarser levels: a smoothing interval per field block
     double ratio = 2.5;
     std::vector<Level *> levels;     // levels[0] is P_0
     // coarsest-level dense inverses, one per connected component
@@ -349,6 +358,16 @@ void residual(const CsrView &A, const T *val, const T *x, const T *b, T *y, hipS
 template <typename T>
 void cheb_step(const CsrView &A, const T *val, const T *x_in, const T *b, const T *x_prev, T *x_out, double c1,
                double c2, hipStream_t s);
+// the same step with coefficients per block of contiguous rows (one block per region and
+// field: the field-split smoother); block q holds rows [start[q], start[q+1])
+struct ChebBlocks {
+    int nb;
+    int32_t start[CHEB_BLOCKS + 1];
+    double c1[CHEB_BLOCKS], c2[CHEB_BLOCKS];
+};
+template <typename T>
+void cheb_step_blocks(const CsrView &A, const T *val, const T *x_in, const T *b, const T *x_prev, T *x_out,
+                      const ChebBlocks &cb, hipStream_t s);
 // x += P xc
 template <typename T>
 void prolong_add(const CsrView &P, const T *val, const T *xc, T *x, hipStream_t s);

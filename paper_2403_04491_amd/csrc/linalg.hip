@@ -148,6 +148,35 @@ struct EpiCheb {
     }
 };
 
+// the Chebyshev step with the coefficients of the row's block
+template <typename T, typename A>
+struct EpiChebBlocks {
+    const T *xin, *xprev, *b;
+    T *xout;
+    ChebBlocks cb;
+    __device__ void coef(int32_t row, A &c1, A &c2) const {
+        int q = 0;
+#pragma unroll
+        for (int k = 1; k < CHEB_BLOCKS; ++k) q += (k < cb.nb && row >= cb.start[k]) ? 1 : 0;
+        c1 = A(cb.c1[0]);
+        c2 = A(cb.c2[0]);
+#pragma unroll
+        for (int k = 1; k < CHEB_BLOCKS; ++k)
+            if (q == k) {
+                c1 = A(cb.c1[k]);
+                c2 = A(cb.c2[k]);
+            }
+    }
+    __device__ void operator()(int32_t row, A s) const {
+        A c1, c2;
+        coef(row, c1, c2);
+        const A xi = A(xin[row]);
+        const A r = A(b[row]) - s;
+        const A dn = (c1 != A(0) ? c1 * (xi - (xprev ? A(xprev[row]) : A(0))) : A(0)) + c2 * r;
+        xout[row] = T(xi + dn);
+    }
+};
+
 template <typename T, typename A>
 struct EpiAdd {
     T *x;
@@ -182,6 +211,29 @@ __global__ void __launch_bounds__(TPB) k_cheb(const int64_t *__restrict__ rowptr
     using A = typename Acc<T>::type;
     EpiCheb<T, A> e{xin, xprev, b, xout, A(c1), A(c2), c1 != 0.0};
     stream_rows<T, T, A>(rowptr, col, val, xin, blk, nblk, e);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_cheb_blocks(const int64_t *__restrict__ rowptr,
+                                                     const int32_t *__restrict__ col, const T *__restrict__ val,
+                                                     const T *__restrict__ xin, const int32_t *__restrict__ blk,
+                                                     int nblk, const T *__restrict__ b, const T *__restrict__ xprev,
+                                                     T *__restrict__ xout, ChebBlocks cb) {
+    using A = typename Acc<T>::type;
+    EpiChebBlocks<T, A> e{xin, xprev, b, xout, cb};
+    stream_rows<T, T, A>(rowptr, col, val, xin, blk, nblk, e);
+}
+
+// first field-split step from x = 0: x = c2 b with the row's block coefficient
+template <typename T>
+__global__ void k_cheb_first_blocks(int64_t n, const T *__restrict__ b, T *__restrict__ xout, ChebBlocks cb) {
+    using A = typename Acc<T>::type;
+    EpiChebBlocks<T, A> e{nullptr, nullptr, b, xout, cb};
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
+        A c1, c2;
+        e.coef(int32_t(i), c1, c2);
+        xout[i] = T(c2 * A(b[i]));
+    }
 }
 
 // first Chebyshev step from x = 0: x = c2 b (no operator application)
@@ -599,6 +651,19 @@ void cheb_step(const CsrView &A, const T *val, const T *x_in, const T *b, const 
 }
 
 template <typename T>
+void cheb_step_blocks(const CsrView &A, const T *val, const T *x_in, const T *b, const T *x_prev, T *x_out,
+                      const ChebBlocks &cb, hipStream_t s) {
+    if (A.nrows == 0) return;
+    if (!x_in) {
+        hipLaunchKernelGGL((k_cheb_first_blocks<T>), dim3(stream_grid(A.nrows)), dim3(TPB), 0, s, A.nrows, b, x_out,
+                           cb);
+        return;
+    }
+    hipLaunchKernelGGL((k_cheb_blocks<T>), dim3(block_grid(A.nblk)), dim3(TPB), 0, s, A.rowptr, A.col, val, x_in,
+                       A.blk, int(A.nblk), b, x_prev, x_out, cb);
+}
+
+template <typename T>
 void fb_residual(const FieldBlockView &A, const T *val, const T *x, const T *b, T *y, hipStream_t s) {
     if (A.nblk == 0) return;
     hipLaunchKernelGGL((k_fb_residual<T>), dim3(block_grid(A.nblk)), dim3(TPB), 0, s, A, val, x, b, y);
@@ -695,6 +760,10 @@ template void cheb_step<double>(const CsrView &, const double *, const double *,
                                 double *, double, double, hipStream_t);
 template void cheb_step<float>(const CsrView &, const float *, const float *, const float *, const float *, float *,
                                double, double, hipStream_t);
+template void cheb_step_blocks<double>(const CsrView &, const double *, const double *, const double *,
+                                       const double *, double *, const ChebBlocks &, hipStream_t);
+template void cheb_step_blocks<float>(const CsrView &, const float *, const float *, const float *, const float *,
+                                      float *, const ChebBlocks &, hipStream_t);
 template void fb_residual<double>(const FieldBlockView &, const double *, const double *, const double *, double *,
                                   hipStream_t);
 template void fb_residual<float>(const FieldBlockView &, const float *, const float *, const float *, float *,

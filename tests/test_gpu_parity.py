@@ -217,6 +217,8 @@ AMG_VARIANTS = {
     "galerkin_symmetric3": dict(strength=0.25, coarse_drop=0.0, cheb_degree=3, cheb_pre_degree=3,
                                 coarse_pre_degree=3, coarse_post_degree=3),
     "presmooth_everywhere": dict(cheb_degree=3, cheb_pre_degree=1, coarse_pre_degree=1, coarse_post_degree=2),
+    "field_split_fp32": dict(precision=1, field_split=1),
+    "field_split_presmooth": dict(field_split=1, coarse_pre_degree=2, coarse_post_degree=2),
 }
 
 
@@ -234,6 +236,27 @@ def test_amg_variants_solve_to_oracle(name, lattice_step1):
     assert info.rel_res <= PARITY["rtol"], (info.its, info.rel_res)
     err = block_err(s.info, s.u.cpu().numpy(), ref)
     assert max(err.values()) <= 1e-8, err
+
+
+def test_field_split_retunes_only_the_coarser_levels(lattice_step1):
+    """With field_split = 1 the coarser levels smooth each (region, field) block on its
+    own interval: the V-cycle changes, by a fraction of its size, and stays linear."""
+    case, _ = lattice_step1
+    ys = []
+    for fs in (0, 1):
+        s = KnpSolver(case, amg=amg_opts(field_split=fs))
+        s.assemble(1)
+        N = s.info.N
+        x = torch.as_tensor(np.random.default_rng(5).standard_normal(N), device=DEV)
+        y = torch.empty_like(x)
+        s.ctx.apply(1, x, y)
+        y2 = torch.empty_like(x)
+        s.ctx.apply(1, 2.0 * x, y2)
+        assert float((y2 - 2.0 * y).abs().max()) <= 1e-12 * float(y.abs().max())
+        ys.append(y.cpu().numpy())
+    d = np.linalg.norm(ys[1] - ys[0]) / np.linalg.norm(ys[0])
+    print(f"  field split changes the V-cycle by {d:.2e} (relative)", flush=True)
+    assert 0.0 < d < 0.5
 
 
 def test_coarse_drop_thins_the_coarse_levels(lattice_step1):
@@ -446,6 +469,9 @@ def test_error_paths():
     assert ei.value.status == 1
     with pytest.raises(knp.KnpError) as ei:
         s.ctx.amg_setup(amg_opts(operator_step=2))
+    assert ei.value.status == 1
+    with pytest.raises(knp.KnpError) as ei:
+        s.ctx.amg_setup(amg_opts(field_split=2))
     assert ei.value.status == 1
     # membrane models: unknown codes and invalid Kir-Na/K parameters are argument errors;
     # cells of other models ignore the pump parameters
