@@ -130,14 +130,14 @@ def roofline_of(timers, precision=None):
                   "avg_launch_us": round(avg_s * 1e6, 2), "launches": t["launches"]}
 
 
-def cpu_baseline(per_pitch, n_steps, log):
+def cpu_baseline(per_pitch, n_steps, log, passive="leak"):
     """The oracle (float64 assembly + SuperLU) on a reduced member of the same
     lattice family, timed on this host."""
     import numpy as np
     from knp_inputs import config_case
     from oracle.assemble import Assembler, initial_gates, initial_state
     from oracle.timeloop import step as oracle_step
-    case = config_case(3, per_pitch=per_pitch, n_steps=n_steps)
+    case = config_case(3, per_pitch=per_pitch, n_steps=n_steps, passive=passive)
     asm = Assembler(case)
     u = initial_state(case, asm.lay)
     w = initial_gates(case, asm.lay)
@@ -621,7 +621,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("[cpu baseline]")
-        cpu = cpu_baseline(args.cpu_per_pitch, args.cpu_steps, log)
+        cpu = cpu_baseline(args.cpu_per_pitch, args.cpu_steps, log, args.passive)
     out = {
         "metric": "time steps/s at ~1e7 unknowns (FP64 vs FP32-AMG), GMRES its/step, HBM GB/s",
         "value": round(head["steps_per_s"], 3),
