@@ -101,6 +101,7 @@ class AdjointProblem:
         carry = torch.zeros(N, dtype=torch.float64, device=s.dev)
         tbar = torch.zeros(s.info.n_cells, dtype=torch.float64, device=s.dev)
         starts = sorted(ckpt)
+        lam_next = None       # lambda_{n+1}: the initial guess of step n's adjoint solve
         for k in range(len(starts) - 1, -1, -1):
             a = starts[k]
             b = starts[k + 1] if k + 1 < len(starts) else case.n_steps
@@ -116,8 +117,13 @@ class AdjointProblem:
                 s.u = u_prev
                 s.theta = theta
                 s.assemble(n)                      # A_{n-1} for this step
-                lam = torch.zeros(N, dtype=torch.float64, device=s.dev)
+                # the adjoint state changes little from one step to the next, as the forward
+                # state does, so the later step's solution starts the solve (the forward
+                # solves start from u_{n-1} the same way)
+                lam = lam_next.clone() if lam_next is not None else torch.zeros(N, dtype=torch.float64,
+                                                                               device=s.dev)
                 info, ok = s.ctx.adjoint_solve(rhs, lam, self.adj_opts, allow_noconv=True)
+                lam_next = lam
                 if not ok and not info.rel_res <= self.adj_accept:
                     raise RuntimeError(f"adjoint solve of step {n} stalled at relative residual "
                                        f"{info.rel_res:.3e} (rtol {self.adj_opts.rtol:g}, accepted up to "
