@@ -101,7 +101,7 @@ class AdjointProblem:
         carry = torch.zeros(N, dtype=torch.float64, device=s.dev)
         tbar = torch.zeros(s.info.n_cells, dtype=torch.float64, device=s.dev)
         starts = sorted(ckpt)
-        lam_next = None       # lambda_{n+1}: the initial guess of step n's adjoint solve
+        lam_next = lam_next2 = None   # lambda_{n+1}, lambda_{n+2}: the initial guess of step n
         for k in range(len(starts) - 1, -1, -1):
             a = starts[k]
             b = starts[k + 1] if k + 1 < len(starts) else case.n_steps
@@ -118,12 +118,16 @@ class AdjointProblem:
                 s.theta = theta
                 s.assemble(n)                      # A_{n-1} for this step
                 # the adjoint state changes little from one step to the next, as the forward
-                # state does, so the later step's solution starts the solve (the forward
-                # solves start from u_{n-1} the same way)
-                lam = lam_next.clone() if lam_next is not None else torch.zeros(N, dtype=torch.float64,
-                                                                               device=s.dev)
+                # state does, so the solve starts from the later steps' solutions, linearly
+                # extrapolated once two are known
+                if lam_next is None:
+                    lam = torch.zeros(N, dtype=torch.float64, device=s.dev)
+                elif lam_next2 is None:
+                    lam = lam_next.clone()
+                else:
+                    lam = 2.0 * lam_next - lam_next2
                 info, ok = s.ctx.adjoint_solve(rhs, lam, self.adj_opts, allow_noconv=True)
-                lam_next = lam
+                lam_next2, lam_next = lam_next, lam
                 if not ok and not info.rel_res <= self.adj_accept:
                     raise RuntimeError(f"adjoint solve of step {n} stalled at relative residual "
                                        f"{info.rel_res:.3e} (rtol {self.adj_opts.rtol:g}, accepted up to "
