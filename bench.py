@@ -526,6 +526,8 @@ def main():
     ap.add_argument("--coarse-pre-degree", type=int, default=0)
     ap.add_argument("--coarse-post-degree", type=int, default=1)
     ap.add_argument("--coarse-max", type=int, default=2000)
+    ap.add_argument("--shared-ion-aggregates", type=int, default=0, choices=[0, 1],
+                    help="1: the finest level's Na and Cl blocks reuse the K block's aggregates")
     ap.add_argument("--field-split", type=int, default=0, choices=[0, 1],
                     help="1: a smoothing interval per (region, field) block on the coarser levels")
     ap.add_argument("--passive", choices=["leak", "kir"], default="leak",
@@ -595,7 +597,8 @@ def main():
     amg_kw = dict(cheb_degree=args.cheb_degree, cheb_ratio=args.cheb_ratio, strength=args.strength,
                   coarse_drop=args.coarse_drop, cheb_pre_degree=args.cheb_pre_degree,
                   coarse_pre_degree=args.coarse_pre_degree, coarse_post_degree=args.coarse_post_degree,
-                  coarse_max=args.coarse_max, field_split=args.field_split)
+                  coarse_max=args.coarse_max, field_split=args.field_split,
+                  shared_ion_aggregates=args.shared_ion_aggregates)
     solver = KnpSolver(case, solve=solve_opts(rtol=1e-6, restart=args.restart, max_it=2000))
     torch.cuda.synchronize()
     t_upload = time.perf_counter() - t0

@@ -109,6 +109,9 @@ typedef struct {
                                is smoothed on its own interval [g_q/cheb_ratio, g_q]
                                (g_q its Gershgorin bound), as a field-split AMG
                                would; 0: one interval per level                  */
+    int32_t shared_ion_aggregates;  /* 1: the Na+ and Cl- blocks of the finest level
+                               reuse the aggregates of the K+ block (one aggregation
+                               for the three ion blocks); 0: each block its own   */
 } knp_amg_opts;
 
 typedef struct {
@@ -193,7 +196,8 @@ knp_status knp_assemble_step(knp_ctx *ctx, double t_n, double dt, const double *
  * knp_assemble_step (else KNP_E_STATE).  opts NULL = defaults (FP64, strength 0.6,
  * Chebyshev smoothing on [lmax/2.5, lmax] of degree 0 before and 5 after the coarse
  * correction on the finest level and 0 and 1 on the coarser levels, coarse_max
- * 2000, max_levels 20, coarse_drop 0.01, operator_step 0, field_split 0). */
+ * 2000, max_levels 20, coarse_drop 0.01, operator_step 0, field_split 0,
+ * shared_ion_aggregates 0). */
 knp_status knp_amg_setup(knp_ctx *ctx, const knp_amg_opts *opts);
 
 /* Shape of the hierarchy built by knp_amg_setup: number of levels (<= 32) and,

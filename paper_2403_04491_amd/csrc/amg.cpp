@@ -472,7 +472,26 @@ void amg_build(Amg &amg, const HostMesh &m, const std::vector<double> &p0_vals, 
         std::vector<int32_t> scol;
         strength(L.A, o.strength, srow, scol);
         std::vector<int32_t> agg;
-        const int64_t nc = aggregate(n, srow, scol, agg);
+        int64_t nc = aggregate(n, srow, scol, agg);
+        if (H.empty() && o.shared_ion_aggregates == 1) {
+            // the Na+ and Cl- blocks of each region take the aggregates of its K+ block
+            // (the three ion blocks share their pattern and differ by tau_k only); the
+            // aggregates they had are dropped and the rest renumbered in order
+            std::vector<int64_t> id(size_t(3) * size_t(nc), -1);
+            for (int r = 0; r < 2; ++r)
+                for (int64_t j = 0; j < m.Nr[r]; ++j) {
+                    const int64_t base = m.off[r] + 4 * j;
+                    agg[base + 0] = int32_t(agg[base + 1] + nc);
+                    agg[base + 2] = int32_t(agg[base + 1] + 2 * nc);
+                }
+            int64_t c = 0;
+            for (int64_t i = 0; i < n; ++i) {
+                int64_t &t = id[size_t(agg[i])];
+                if (t < 0) t = c++;
+            }
+            for (int64_t i = 0; i < n; ++i) agg[i] = int32_t(id[size_t(agg[i])]);
+            nc = c;
+        }
         if (double(nc) > 0.85 * double(n)) {   // coarsening stalled: make this the coarsest
             L.blk = RB;
             H.push_back(std::move(L));

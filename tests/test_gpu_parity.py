@@ -219,6 +219,7 @@ AMG_VARIANTS = {
     "presmooth_everywhere": dict(cheb_degree=3, cheb_pre_degree=1, coarse_pre_degree=1, coarse_post_degree=2),
     "field_split_fp32": dict(precision=1, field_split=1),
     "field_split_presmooth": dict(field_split=1, coarse_pre_degree=2, coarse_post_degree=2),
+    "shared_ion_aggregates": dict(precision=1, shared_ion_aggregates=1),
 }
 
 
@@ -472,6 +473,9 @@ def test_error_paths():
     assert ei.value.status == 1
     with pytest.raises(knp.KnpError) as ei:
         s.ctx.amg_setup(amg_opts(field_split=2))
+    assert ei.value.status == 1
+    with pytest.raises(knp.KnpError) as ei:
+        s.ctx.amg_setup(amg_opts(shared_ion_aggregates=2))
     assert ei.value.status == 1
     # membrane models: unknown codes and invalid Kir-Na/K parameters are argument errors;
     # cells of other models ignore the pump parameters
