@@ -132,8 +132,15 @@ def roofline_of(timers, precision=None):
 
 def cpu_baseline(per_pitch, n_steps, log, passive="leak"):
     """The oracle (float64 assembly + SuperLU) on a reduced member of the same
-    lattice family, timed on this host."""
+    lattice family, timed on this host with every thread pool held to one thread
+    (SuperLU is serial; the cap keeps any BLAS call in the assembly serial too)."""
     import numpy as np
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):
+        return _cpu_baseline(per_pitch, n_steps, log, passive, np)
+
+
+def _cpu_baseline(per_pitch, n_steps, log, passive, np):
     from knp_inputs import config_case
     from oracle.assemble import Assembler, initial_gates, initial_state
     from oracle.timeloop import step as oracle_step
@@ -153,7 +160,7 @@ def cpu_baseline(per_pitch, n_steps, log, passive="leak"):
                       f"{case.shape[0]}^3 grid, N={asm.lay.N} unknowns (not the full ~1e7 problem, "
                       f"which the direct solver cannot factor); median s/step {per_step:.2f}",
             "host_cores_available": len(os.sched_getaffinity(0)),
-            "threads_env": {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS")}}
+            "threads": "thread pools limited to 1 while timed"}
 
 
 def kernels_only(solver, args, amg_kw, log):
@@ -288,17 +295,19 @@ def model_a_bench(args, log):
             f"{p_n['ms_per_step_P_n_steps_2_on']} ms/step with the rebuild")
     cpu = None
     if not args.no_cpu_baseline:
+        from threadpoolctl import threadpool_limits
         from oracle.assemble import Assembler, initial_gates, initial_state
         from oracle.timeloop import step as oracle_step
         oc = model_a_evolution_case(nx=args.ma_cpu_nx, membrane="hh", n_steps=args.ma_cpu_steps)
         asm = Assembler(oc)
         u, w = initial_state(oc, asm.lay), initial_gates(oc, asm.lay)
         ts = []
-        for n in range(1, args.ma_cpu_steps + 1):
-            t0 = time.perf_counter()
-            u, w, _ = oracle_step(asm, u, w, n, oc.dt)
-            ts.append(time.perf_counter() - t0)
-            log(f"  oracle step {n}: {ts[-1]:.2f} s (N={asm.lay.N})")
+        with threadpool_limits(limits=1):          # one thread, as "cores" states
+            for n in range(1, args.ma_cpu_steps + 1):
+                t0 = time.perf_counter()
+                u, w, _ = oracle_step(asm, u, w, n, oc.dt)
+                ts.append(time.perf_counter() - t0)
+                log(f"  oracle step {n}: {ts[-1]:.2f} s (N={asm.lay.N})")
         per = float(np.median(ts))
         cpu = {"value": round(1.0 / per, 4), "unit": "time steps/s", "cores": 1, "kind": "oracle",
                "sample": f"{args.ma_cpu_steps} oracle steps (assembly + SuperLU) of the same Model A case at "
