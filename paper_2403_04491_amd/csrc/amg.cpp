@@ -28,6 +28,7 @@
 #include <numeric>
 #include <type_traits>
 
+#include "dense.h"
 #include "knp_internal.h"
 
 namespace knp {
@@ -272,38 +273,6 @@ struct HostLevel {
     double lmax;
     std::vector<int8_t> blk;   // (region, field) block of each row: 4 r + f
 };
-
-void invert_dense(int n, std::vector<double> &a) {   // Gauss-Jordan, partial pivoting, in place
-    std::vector<int> piv(n);
-    std::vector<double> inv(size_t(n) * n, 0.0);
-    for (int i = 0; i < n; ++i) inv[size_t(i) * n + i] = 1.0;
-    for (int c = 0; c < n; ++c) {
-        int p = c;
-        for (int r = c + 1; r < n; ++r)
-            if (std::fabs(a[size_t(r) * n + c]) > std::fabs(a[size_t(p) * n + c])) p = r;
-        if (a[size_t(p) * n + c] == 0.0) throw Error{KNP_E_NUMERIC, "singular coarsest-level block"};
-        if (p != c)
-            for (int k = 0; k < n; ++k) {
-                std::swap(a[size_t(p) * n + k], a[size_t(c) * n + k]);
-                std::swap(inv[size_t(p) * n + k], inv[size_t(c) * n + k]);
-            }
-        const double d = 1.0 / a[size_t(c) * n + c];
-        for (int k = 0; k < n; ++k) {
-            a[size_t(c) * n + k] *= d;
-            inv[size_t(c) * n + k] *= d;
-        }
-        for (int r = 0; r < n; ++r) {
-            if (r == c) continue;
-            const double f = a[size_t(r) * n + c];
-            if (f == 0.0) continue;
-            for (int k = 0; k < n; ++k) {
-                a[size_t(r) * n + k] -= f * a[size_t(c) * n + k];
-                inv[size_t(r) * n + k] -= f * inv[size_t(c) * n + k];
-            }
-        }
-    }
-    a.swap(inv);
-}
 
 }  // namespace
 
@@ -685,6 +654,8 @@ void amg_build(Amg &amg, const HostMesh &m, const std::vector<double> &p0_vals, 
         tot += nb * nb;
     }
     std::vector<double> inv(std::max<int64_t>(1, tot), 0.0);
+    // no exception may leave the parallel region: failures are flagged per component
+    std::vector<char> singular(ncomp, 0);
 #pragma omp parallel for schedule(dynamic, 1)
     for (int32_t c = 0; c < ncomp; ++c) {
         const int64_t s0 = cstart[c], nb = cstart[c + 1] - s0;
@@ -693,9 +664,17 @@ void amg_build(Amg &amg, const HostMesh &m, const std::vector<double> &p0_vals, 
             const int64_t v = order[s0 + p];
             for (int64_t k = C.rowptr[v]; k < C.rowptr[v + 1]; ++k) a[size_t(p) * nb + cloc[C.col[k]]] = C.val[k];
         }
-        invert_dense(int(nb), a);
+        if (!invert_dense(int(nb), a)) {
+            singular[c] = 1;
+            continue;
+        }
         std::copy(a.begin(), a.end(), inv.begin() + boff[c]);
     }
+    for (int32_t c = 0; c < ncomp; ++c)
+        if (singular[c])
+            throw Error{KNP_E_NUMERIC, "singular coarsest-level block (component " + std::to_string(c) + " of " +
+                                           std::to_string(ncomp) + ", " +
+                                           std::to_string(cstart[c + 1] - cstart[c]) + " rows)"};
 
     // upload
     const bool f32 = amg.fp32;
