@@ -25,6 +25,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+# tolerances tried on the last step's system for the FP32-level solve that meets 1e-6 in
+# every block against the FP64 reference
+ACCURACY_RTOLS = (1e-8, 1e-9, 1e-10, 1e-11)
 
 
 def block_errors(info, u, ref):
@@ -37,7 +40,30 @@ def block_errors(info, u, ref):
     return out
 
 
-def run_precision(solver, u0, g0, precision, warmup, steps, log, first_restart, amg_kw):
+def block_errors_inf(info, u, ref):
+    import numpy as np
+    Ni, Ne = info.N_i, info.N_e
+    out = {}
+    for k, b in {"c_i": np.r_[0:3 * Ni], "c_e": np.r_[4 * Ni:4 * Ni + 3 * Ne],
+                 "phi": np.r_[3 * Ni:4 * Ni, 4 * Ni + 3 * Ne:4 * (Ni + Ne)]}.items():
+        out[k] = float(np.abs(u[b] - ref[b]).max() / np.abs(ref[b]).max())
+    return out
+
+
+def timed_steps(solver, steps, opts=None):
+    """Exactly `steps` steps (assemble + solve) between two device synchronisations."""
+    import torch
+    torch.cuda.synchronize()
+    its = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        info = solver.step(opts=opts)
+        its.append(info.its)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, its
+
+
+def run_precision(solver, u0, g0, precision, warmup, steps, log, first_restart, amg_kw, n_total):
     import torch
     from paper_2403_04491_amd import amg_opts, solve_opts
     solver.u = u0.clone()
@@ -47,6 +73,7 @@ def run_precision(solver, u0, g0, precision, warmup, steps, log, first_restart, 
     solver.amg_ready = False
     t_setup = time.perf_counter()
     its_w = []
+    first = {}
     for w in range(warmup):
         if w == 0:
             solver.assemble()
@@ -54,30 +81,73 @@ def run_precision(solver, u0, g0, precision, warmup, steps, log, first_restart, 
             setup_s = time.perf_counter() - t_setup
             # the first step absorbs the seeded per-node noise; its preconditioned
             # spectrum needs a Krylov polynomial of high degree (long restart)
+            t1 = time.perf_counter()
             x, info, ok = solver.solve(opts=solve_opts(rtol=1e-6, restart=first_restart, max_it=4000))
+            torch.cuda.synchronize()
+            first = {"its": info.its, "solve_s": round(time.perf_counter() - t1, 3), "restart": first_restart,
+                     "rel_res": info.rel_res}
             solver.u = x
             solver.n += 1
         else:
             info = solver.step()
         its_w.append(info.its)
         log(f"  warmup step {solver.n}: its={info.its} rel_res={info.rel_res:.2e}")
-    torch.cuda.synchronize()
+    after_warmup = (solver.u.clone(), solver.gates.clone(), solver.n)
     solver.ctx.timing(True)
-    its = []
-    t0 = time.perf_counter()
-    for k in range(steps):
-        info = solver.step()
-        its.append(info.its)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    elapsed, its = timed_steps(solver, steps)
     timers = solver.ctx.timing_read()
     solver.ctx.timing(False)
     log(f"  timed {steps} steps in {elapsed:.3f} s, its={its}")
+    # the rest of the workload's horizon, untimed, so that the error statements below are
+    # taken on its last step
+    rest = []
+    while solver.n < n_total - 1:
+        rest.append(solver.step().its)
+    final_prev = (solver.u.clone(), solver.gates.clone(), solver.n)
+    if solver.n < n_total:
+        rest.append(solver.step().its)
+    if rest:
+        log(f"  untimed steps {final_prev[2] - len(rest) + 2}..{solver.n}: its={rest}")
     hier = solver.ctx.amg_stats()
     log(f"  hierarchy rows {hier['rows']} nnz {hier['nnz']}")
     return {"hierarchy": hier, "steps_per_s": steps / elapsed, "ms_per_step": 1e3 * elapsed / steps, "its": its,
-            "its_warmup": its_w, "amg_setup_s": setup_s, "timers": timers,
-            "u": solver.u.cpu().numpy()}
+            "its_warmup": its_w, "its_untimed_rest": rest, "amg_setup_s": setup_s, "first_step": first,
+            "timers": timers, "u": solver.u.clone(), "final_prev": final_prev, "after_warmup": after_warmup}
+
+
+def final_system_errors(solver, run, precision, amg_kw, log, rtols=()):
+    """The last step's system re-assembled from the run's own u_{n-1} and solved with
+    FP64 levels to rtol 1e-12 (FGMRES(60)): per-block error (l2 and element-wise) of the
+    run's solution against it.  With rtols, the same system is also solved with the run's
+    own levels at each of them, from u_{n-1}, and those errors are reported too."""
+    import torch
+    from paper_2403_04491_amd import amg_opts, solve_opts
+    u_prev, g_prev, n_prev = run["final_prev"]
+    solver.u, solver.gates, solver.n = u_prev.clone(), g_prev.clone(), n_prev
+    solver.assemble()                              # the same A_{n-1}, f_n (deterministic)
+    info = solver.info
+    trial = {}
+    for rt in rtols:
+        x, inf_, ok = solver.solve(allow_noconv=True, opts=solve_opts(rtol=rt, restart=30, max_it=4000))
+        trial[rt] = (x, inf_.its)
+    if precision != 0:
+        solver.ctx.amg_setup(amg_opts(precision=0, **amg_kw))
+    ref, inf_ref, ok_ref = solver.solve(allow_noconv=True, opts=solve_opts(rtol=1e-12, restart=60, max_it=6000))
+    torch.cuda.synchronize()
+    r = ref.cpu().numpy()
+    u = run["u"].cpu().numpy()
+    out = {"step": n_prev + 1, "reference": {"levels": "fp64", "rtol": 1e-12, "its": inf_ref.its,
+                                            "rel_res": inf_ref.rel_res, "converged": ok_ref},
+           "l2": block_errors(info, u, r), "elementwise": block_errors_inf(info, u, r)}
+    tr = {}
+    for rt, (x, its) in trial.items():
+        xv = x.cpu().numpy()
+        tr[f"{rt:g}"] = {"its": its, "l2": block_errors(info, xv, r), "elementwise": block_errors_inf(info, xv, r)}
+    if tr:
+        out["at_rtol"] = tr
+    log(f"  final-step error vs FP64 rtol-1e-12 reference ({inf_ref.its} its): l2 {out['l2']}, "
+        f"element-wise {out['elementwise']}")
+    return out
 
 
 # HBM traffic per launch from rocprofv3 counters (FETCH_SIZE, WRITE_SIZE), taken on
@@ -111,7 +181,18 @@ def measured_traffic(kernel, precision):
     return None if k is None else k.get("bytes_per_launch")
 
 
-def roofline_of(timers, precision=None):
+def survey_unit_bytes(kernel, info, precision):
+    """Bytes of one launch in the CSR unit of the byte model the path was planned on
+    (SpMV(A): 12 per nonzero + 24 per row; SpMV(P_0) on the finest level: 12 or 8 per
+    nonzero + 24 or 16 per row for FP64 or FP32 levels), which credits any compression
+    of the stored layout as work done."""
+    if kernel == "spmv_A":
+        return 12.0 * info.nnz_A + 24.0 * info.N
+    per_nz, per_row = (8.0, 16.0) if precision == "fp32_amg" else (12.0, 24.0)
+    return per_nz * info.nnz_P0 + per_row * info.N
+
+
+def roofline_of(timers, precision=None, info=None):
     best = None
     for name in ("spmv_A", "cheb_L0", "resid_L0"):
         t = timers[name]
@@ -123,11 +204,21 @@ def roofline_of(timers, precision=None):
     per_launch_bytes = t["bytes"] / t["launches"]
     avg_s = t["total_ms"] / t["launches"] * 1e-3
     achieved = per_launch_bytes / avg_s / 1e9
-    return best, {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                  "frac": round(achieved / PEAK_HBM_GBS, 4),
-                  "traffic": measured_traffic(best, precision) if precision else None,
-                  "kernel": best, "bytes_per_launch": per_launch_bytes,
-                  "avg_launch_us": round(avg_s * 1e6, 2), "launches": t["launches"]}
+    traffic = measured_traffic(best, precision) if precision else None
+    out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+           "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
+           "kernel": best, "bytes_per_launch": per_launch_bytes,
+           "avg_launch_us": round(avg_s * 1e6, 2), "launches": t["launches"],
+           "convention": "achieved and frac: the kernel's own minimum bytes per launch (its stored layout, "
+                         "each matrix and vector entry once) over its average HIP-event duration; frac_survey: "
+                         "the CSR byte model's unit for the same launch over the same duration",
+           "frac_layout": round(achieved / PEAK_HBM_GBS, 4),
+           "traffic_ratio": None if traffic is None else round(traffic / per_launch_bytes, 3)}
+    if info is not None and precision is not None:
+        sb = survey_unit_bytes(best, info, precision)
+        out["bytes_survey_unit"] = sb
+        out["frac_survey"] = round(sb / avg_s / 1e9 / PEAK_HBM_GBS, 4)
+    return best, out
 
 
 def cpu_baseline(per_pitch, n_steps, log, passive="leak"):
@@ -442,8 +533,9 @@ def adjoint_bench(args, log):
 
 def large_bench(args, log):
     """The 8x8x8 lattice of elongated cells (~1.1e8 unknowns), FP32-stored AMG:
-    device memory after each phase, the first step at rtol 1e-6 against the same
-    system solved to rtol 1e-9 in FP64 FGMRES, then timed steps."""
+    device memory after each phase, the first step at rtol 1e-6, timed steps, then the
+    first step's system solved again with an FP64 hierarchy to rtol 1e-11 as the
+    reference for the first step's error."""
     import numpy as np
     import torch
     from knp_inputs import config_case
@@ -483,16 +575,7 @@ def large_bench(args, log):
     t_first = time.perf_counter() - t0
     log(f"step 1 at rtol 1e-6: {inf1.its} its, rel_res {inf1.rel_res:.2e}, {t_first:.1f} s")
     sample("step 1 (FP32 AMG, rtol 1e-6)")
-    solver.u = x                    # the reference continues from the rtol-1e-6 iterate
-    t0 = time.perf_counter()
-    ref, inf_ref, ok_ref = solver.solve(allow_noconv=True,
-                                        opts=solve_opts(rtol=1e-9, restart=args.large_first_restart, max_it=6000))
-    torch.cuda.synchronize()
-    log(f"step 1 reference at rtol 1e-9: {inf_ref.its} its, rel_res {inf_ref.rel_res:.2e}, "
-        f"{time.perf_counter() - t0:.1f} s")
-    err = block_errors(info, x.cpu().numpy(), ref.cpu().numpy())
-    log(f"  step-1 error of the rtol-1e-6 FP32-AMG solve vs the rtol-1e-9 solve: {err}")
-    del ref
+    x1 = x.clone()
     solver.u = x
     solver.n = 1
     its, times = [], []
@@ -505,6 +588,28 @@ def large_bench(args, log):
         its.append(inf.its)
         log(f"  step {solver.n}: {inf.its} its, rel_res {inf.rel_res:.2e}, {times[-1] * 1e3:.0f} ms")
     sample("timed steps")
+    # the reference for step 1: the same system (re-assembled from u_0; the assembly is
+    # deterministic) with the hierarchy rebuilt in FP64 (levels, Arnoldi and residual in
+    # FP64), solved from the rtol-1e-6 iterate to rtol 1e-11
+    solver.u = u0
+    solver.assemble(1)
+    t0 = time.perf_counter()
+    solver.ctx.amg_setup(amg_opts(precision=0))
+    torch.cuda.synchronize()
+    t_setup64 = time.perf_counter() - t0
+    sample("FP64 hierarchy for the reference")
+    solver.u = x1
+    t0 = time.perf_counter()
+    ref, inf_ref, ok_ref = solver.solve(allow_noconv=True,
+                                        opts=solve_opts(rtol=1e-11, restart=args.large_first_restart, max_it=8000))
+    torch.cuda.synchronize()
+    log(f"step 1 reference (FP64 levels) at rtol 1e-11: {inf_ref.its} its, rel_res {inf_ref.rel_res:.2e}, "
+        f"{time.perf_counter() - t0:.1f} s")
+    sample("step 1 reference (FP64 levels, rtol 1e-11)")
+    xv, rv = x1.cpu().numpy(), ref.cpu().numpy()
+    err = {"l2": block_errors(info, xv, rv), "elementwise": block_errors_inf(info, xv, rv)}
+    log(f"  step-1 error of the rtol-1e-6 FP32-AMG solve vs the FP64-level rtol-1e-11 solve: {err}")
+    del ref, xv, rv
     timed = times[1:] if len(times) > 1 else times
     ms = 1e3 * float(np.median(timed))
     out = {
@@ -519,8 +624,10 @@ def large_bench(args, log):
         "its_per_step": its, "step_ms": [round(t * 1e3, 1) for t in times],
         "first_step": {"restart": args.large_first_restart, "its": inf1.its, "rel_res": inf1.rel_res,
                        "converged": ok1, "s": round(t_first, 2),
+                       "reference": "same system, FP64 hierarchy (levels, Arnoldi, residual), rtol 1e-11",
                        "reference_its": inf_ref.its, "reference_rel_res": inf_ref.rel_res,
-                       "reference_converged": ok_ref, "rel_err_vs_reference": err},
+                       "reference_converged": ok_ref, "reference_fp64_setup_s": round(t_setup64, 1),
+                       "rel_err_vs_reference": err},
         "setup_s": {"mesh_upload": round(t_upload, 1), "first_assembly_and_amg_setup": round(t_setup, 1)},
         "amg_hierarchy": stats,
         "device_memory_gib": mem, "device_memory_total_gib": round(total / 2**30, 1),
@@ -536,6 +643,11 @@ def main():
     ap.add_argument("--per-pitch", type=int, default=33, help="grid intervals per cell pitch (33 = ~1e7 unknowns)")
     ap.add_argument("--precision", choices=["both", "fp64", "fp32"], default="both")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--horizon", type=int, default=None,
+                    help="steps of the workload to run (default its 50; the steps after the timed ones "
+                         "are untimed); 0 stops after the timed steps")
+    ap.add_argument("--no-error-check", action="store_true",
+                    help="skip the re-solves of the last step's system (FP64 levels, rtol 1e-12)")
     ap.add_argument("--cpu-per-pitch", type=int, default=4)
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--first-restart", type=int, default=200,
@@ -614,7 +726,7 @@ def main():
     from paper_2403_04491_amd import KnpSolver, solve_opts
 
     t0 = time.perf_counter()
-    case = config_case(3, per_pitch=args.per_pitch, n_steps=args.warmup + args.steps, passive=args.passive)
+    case = config_case(3, per_pitch=args.per_pitch, passive=args.passive)
     t_gen = time.perf_counter() - t0
     log(f"case {case.name}: {case.n_vert} vertices, {case.n_elem} tets, generated in {t_gen:.1f} s")
     t0 = time.perf_counter()
@@ -630,17 +742,48 @@ def main():
     u0 = solver.u.clone()
     g0 = solver.gates.clone()
     runs = {}
+    errs = {}
+    accurate = None
+    n_total = max(case.n_steps if args.horizon is None else args.horizon, args.warmup + args.steps)
     order = {"both": [0, 1], "fp64": [0], "fp32": [1]}[args.precision]
     for prec in order:
         name = "fp64" if prec == 0 else "fp32_amg"
         log(f"[{name}]")
         runs[name] = run_precision(solver, u0, g0, prec, args.warmup, args.steps, log, args.first_restart,
-                                   amg_kw)
+                                   amg_kw, n_total)
+        if args.no_error_check:
+            continue
+        rtols = ACCURACY_RTOLS if prec == 1 else ()
+        errs[name] = final_system_errors(solver, runs[name], prec, amg_kw, log, rtols)
+        if prec == 1:
+            # the loosest of the tried tolerances whose solution of the last step's system
+            # meets 1e-6 in every block, element-wise; K steps at it from the same state
+            ok = [rt for rt in ACCURACY_RTOLS
+                  if max(errs[name]["at_rtol"][f"{rt:g}"]["elementwise"].values()) <= 1e-6]
+            if ok:
+                rt = max(ok)
+                from paper_2403_04491_amd import amg_opts, solve_opts
+                solver.amg_opts = amg_opts(precision=1, **amg_kw)
+                solver.ctx.amg_setup(solver.amg_opts)
+                u_w, g_w, n_w = runs[name]["after_warmup"]
+                solver.u, solver.gates, solver.n = u_w.clone(), g_w.clone(), n_w
+                el, its_acc = timed_steps(solver, args.steps, opts=solve_opts(rtol=rt, restart=args.restart,
+                                                                              max_it=4000))
+                accurate = {"rtol": rt, "steps_per_s": round(args.steps / el, 3),
+                            "ms_per_step": round(1e3 * el / args.steps, 2),
+                            "its_per_step": round(sum(its_acc) / len(its_acc), 2),
+                            "same_steps_as_value": f"{n_w + 1}..{n_w + args.steps}"}
+                log(f"  FP32 levels at rtol {rt:g}: {accurate['steps_per_s']} steps/s, its={its_acc}")
     head = runs.get("fp32_amg") or runs["fp64"]
-    kernel, roof = roofline_of(head["timers"], "fp32_amg" if "fp32_amg" in runs else "fp64")
+    kernel, roof = roofline_of(head["timers"], "fp32_amg" if "fp32_amg" in runs else "fp64", info)
     extra = {}
     if "fp64" in runs and "fp32_amg" in runs:
-        extra["fp32_amg_vs_fp64_final_step_rel_err"] = block_errors(info, runs["fp32_amg"]["u"], runs["fp64"]["u"])
+        extra["fp32_amg_vs_fp64_final_step_rel_err"] = block_errors(info, runs["fp32_amg"]["u"].cpu().numpy(),
+                                                                    runs["fp64"]["u"].cpu().numpy())
+    if errs:
+        extra["final_step_error_vs_fp64_reference"] = errs
+    if accurate:
+        extra["fp32_amg_at_accuracy_1e-6"] = accurate
     cpu = None
     if not args.no_cpu_baseline:
         log("[cpu baseline]")
@@ -672,6 +815,9 @@ def main():
                                 for k, r in runs.items()},
         "setup_s": {"mesh_upload": round(t_upload, 2),
                     **{f"amg_setup_{k}": round(r["amg_setup_s"], 2) for k, r in runs.items()}},
+        "first_step": {k: r["first_step"] for k, r in runs.items()},
+        "its_warmup": {k: r["its_warmup"] for k, r in runs.items()},
+        "steps_in_workload": n_total,
         "kernel_gbs": {k: {n: round(t["bytes"] / (t["total_ms"] * 1e-3) / 1e9, 1)
                            for n, t in r["timers"].items() if t["launches"] and t["bytes"] > 0}
                        for k, r in runs.items()},

@@ -36,6 +36,17 @@ def block_err(info, u, ref):
     return {k: float(np.linalg.norm(u[b] - ref[b]) / np.linalg.norm(ref[b])) for k, b in blocks(info).items()}
 
 
+def block_err_inf(info, u, ref):
+    """Element-wise: max |u - u_ref| / max |u_ref| per block, so that an error confined to
+    a few entries (the membrane vertices, say) cannot hide in a block's l2 norm."""
+    return {k: float(np.abs(u[b] - ref[b]).max() / np.abs(ref[b]).max()) for k, b in blocks(info).items()}
+
+
+def worst_err(info, u, ref):
+    """(worst l2 block error, worst element-wise block error)."""
+    return max(block_err(info, u, ref).values()), max(block_err_inf(info, u, ref).values())
+
+
 def T(x):
     return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device=DEV)
 
@@ -235,8 +246,8 @@ def test_amg_variants_solve_to_oracle(name, lattice_step1):
     s = KnpSolver(case, amg=amg_opts(**AMG_VARIANTS[name]), solve=solve_opts(**PARITY))
     info = s.step()
     assert info.rel_res <= PARITY["rtol"], (info.its, info.rel_res)
-    err = block_err(s.info, s.u.cpu().numpy(), ref)
-    assert max(err.values()) <= 1e-8, err
+    l2, inf = worst_err(s.info, s.u.cpu().numpy(), ref)
+    assert l2 <= 1e-8 and inf <= 1e-8, (l2, inf)
 
 
 def test_field_split_retunes_only_the_coarser_levels(lattice_step1):
@@ -309,31 +320,38 @@ def run_both(case, n_steps, precision=0):
     return s, gpu, ref, its
 
 
-@pytest.mark.parametrize("name,steps,precision,tol", [
-    ("cfg1", 10, 0, 1e-8),
-    ("cfg1", 3, 1, 1e-6),
-    ("modelA3d_nx8_hh", 4, 0, 1e-8),
-    ("lattice4_pp4", 2, 0, 1e-8),
-    ("modelA3d_nx8_kir", 4, 0, 1e-8),
-    ("modelA3d_nx8_kir", 3, 1, 1e-6),
-    ("lattice4_pp4_kir", 2, 0, 1e-8),
+# inc_tol bounds the error of each step's increment u_n - u_{n-1} relative to the oracle's
+# increment, per block: the solution bars alone leave it loose, since a step moves u by only
+# ~1e-4 of its size.  The floor is the solution error of both sides (LU leaves ~2e-10
+# relative in the potentials) over the size of a step's change; observed: 5e-6 (2D leak
+# cell, 10 steps), 1.5e-7 to 3.5e-7 (3D single cell), 1.8e-8 (lattices).  The bars leave
+# about 6x of room for other rounding orders.
+@pytest.mark.parametrize("name,steps,precision,tol,inc_tol", [
+    ("cfg1", 10, 0, 1e-8, 3e-5),
+    ("cfg1", 3, 1, 1e-6, 3e-5),
+    ("modelA3d_nx8_hh", 4, 0, 1e-8, 2e-6),
+    ("lattice4_pp4", 2, 0, 1e-8, 2e-7),
+    ("modelA3d_nx8_kir", 4, 0, 1e-8, 2e-6),
+    ("modelA3d_nx8_kir", 3, 1, 1e-6, 2e-6),
+    ("lattice4_pp4_kir", 2, 0, 1e-8, 2e-7),
 ])
-def test_time_steps_match_oracle(name, steps, precision, tol):
+def test_time_steps_match_oracle(name, steps, precision, tol, inc_tol):
     case = ASM_CASES[name]()
     print(f"[steps] {name} steps={steps} precision={precision}", flush=True)
     s, gpu, ref, its = run_both(case, steps, precision)
-    worst = worst_inc = 0.0
+    worst = worst_inf = worst_inc = 0.0
     for n in range(1, steps + 1):
-        e = block_err(s.info, gpu[n], ref[n])
-        worst = max(worst, max(e.values()))
-        # the step's increment, a stricter diagnostic (concentrations change little per step)
+        l2, inf = worst_err(s.info, gpu[n], ref[n])
+        worst, worst_inf = max(worst, l2), max(worst_inf, inf)
+        # the step's increment, a stricter measure (concentrations change little per step)
         for b in blocks(s.info).values():
             d_ref = ref[n][b] - ref[n - 1][b]
             worst_inc = max(worst_inc, float(np.linalg.norm((gpu[n][b] - gpu[n - 1][b]) - d_ref)
                                              / np.linalg.norm(d_ref)))
-    print(f"  its per step {its}, worst block error {worst:.2e}, worst increment error {worst_inc:.2e}",
-          flush=True)
-    assert worst <= tol
+    print(f"  its per step {its}, worst block error l2 {worst:.2e} element-wise {worst_inf:.2e}, "
+          f"worst increment error {worst_inc:.2e}", flush=True)
+    assert worst <= tol and worst_inf <= tol
+    assert worst_inc <= inc_tol
 
 
 def test_model_a_evolution_matches_oracle():
@@ -361,7 +379,7 @@ def test_model_a_evolution_matches_oracle():
             u = s.u.cpu().numpy()
             worst = max(worst, max(block_err(s.info, u, ref["u"][n]).values()))
             one, _, _ = oracle_step(asm, u_prev, w_prev, n, case.dt)
-            worst_step = max(worst_step, max(block_err(s.info, u, one).values()))
+            worst_step = max(worst_step, *worst_err(s.info, u, one))
     print(f"  iterations min/mean/max {min(its)}/{np.mean(its):.1f}/{max(its)}, worst block error "
           f"{worst:.2e} (one step from the same state {worst_step:.2e}), worst phi_M error "
           f"{worst_phiM:.2e} V", flush=True)
@@ -372,6 +390,65 @@ def test_model_a_evolution_matches_oracle():
     # over these 300 steps, so the two trajectories are held to 6e-8
     assert worst <= 6e-8
     assert worst_phiM <= 1e-8 * 0.1          # 1e-8 of the 0.1 V scale of an action potential
+
+
+def worst_err_thermal(info, u, ref, psi):
+    """worst_err with the potential block judged against max(its own size, the thermal
+    voltage RT/F per entry): when the membrane potential crosses 0 mV during an action
+    potential the potentials' norm falls by ~70x and a purely relative measure reads the
+    same absolute error (the oracle's own LU error included) 70x larger."""
+    l2 = inf = 0.0
+    for k, b in blocks(info).items():
+        d = u[b] - ref[b]
+        nrm, mx = np.linalg.norm(ref[b]), np.abs(ref[b]).max()
+        if k == "phi":
+            nrm, mx = max(nrm, psi * np.sqrt(len(b))), max(mx, psi)
+        l2, inf = max(l2, float(np.linalg.norm(d) / nrm)), max(inf, float(np.abs(d).max() / mx))
+    return l2, inf
+
+
+def test_config2_protocol_matches_oracle_every_step():
+    """The protocol of the 3D Model A workload (one cell, Hodgkin-Huxley membrane with the
+    stimulus, dt = 0.05 ms, 100 steps: one action potential) at N_x = 8, every step against
+    one oracle step from the GPU's own previous state, element-wise, and the trajectory
+    against the oracle's.  Potentials are judged against max(their size, RT/F) (see
+    worst_err_thermal); the plain relative errors are printed."""
+    case = model_a_case(3, 8, "hh", 5e-5, 100, cfg_id=2)
+    prm = case.params
+    psi = prm["R"] * prm["T"] / prm["F"]
+    print(f"[config-2 protocol] {case.name} steps=100", flush=True)
+    ref = timeloop.run(case)
+    asm = ref["asm"]
+    lay = asm.lay
+    s = KnpSolver(case, amg=amg_opts(precision=0), solve=solve_opts(**PARITY))
+    ri, re = s.membrane_rows()
+    order = np.argsort(s.gamma)
+    worst_step = worst_traj = worst_phiM = worst_plain = 0.0
+    peak = -1.0
+    its = []
+    for n in range(1, 101):
+        u_prev, w_prev = s.u.cpu().numpy(), s.gates.cpu().numpy()
+        its.append(s.step().its)
+        u = s.u.cpu().numpy()
+        one, w_one, _ = oracle_step(asm, u_prev, w_prev, n, case.dt)
+        l2, inf = worst_err_thermal(s.info, u, one, psi)
+        assert l2 <= 1e-8 and inf <= 1e-8, (n, l2, inf)
+        assert np.abs(s.gates.cpu().numpy() - w_one).max() <= 1e-13, n
+        worst_step = max(worst_step, l2, inf)
+        worst_plain = max(worst_plain, *worst_err(s.info, u, one))
+        worst_traj = max(worst_traj, *worst_err_thermal(s.info, u, ref["u"][n], psi))
+        phiM = (s.u[ri] - s.u[re]).cpu().numpy()[order]
+        _, _, ref_phiM = gamma_values(lay, ref["u"][n])
+        worst_phiM = max(worst_phiM, float(np.abs(phiM - ref_phiM[np.argsort(lay.gamma)]).max()))
+        peak = max(peak, float(phiM.mean()))
+    print(f"  iterations min/mean/max {min(its)}/{np.mean(its):.1f}/{max(its)}, one step from the same state "
+          f"{worst_step:.2e} (plain relative {worst_plain:.2e}), trajectory {worst_traj:.2e}, phi_M "
+          f"{worst_phiM:.2e} V, peak phi_M {peak * 1e3:.1f} mV", flush=True)
+    assert peak > 0.0                        # the stimulus fires an action potential
+    # the time map amplifies perturbations during the action potential (as in the 2D
+    # evolution test), so the trajectory is held to the same 6e-8
+    assert worst_traj <= 6e-8
+    assert worst_phiM <= 1e-8 * 0.1
 
 
 def test_time_dependent_p_n_matches_oracle():
@@ -390,8 +467,8 @@ def test_time_dependent_p_n_matches_oracle():
             u_prev, w_prev = s.u.cpu().numpy(), s.gates.cpu().numpy()
             its[op].append(s.step().its)
             one, _, _ = oracle_step(asm, u_prev, w_prev, n, case.dt)   # one step, same state
-            e = block_err(s.info, s.u.cpu().numpy(), one)
-            assert max(e.values()) <= 1e-8, (op, n, e)
+            l2, inf = worst_err(s.info, s.u.cpu().numpy(), one)
+            assert l2 <= 1e-8 and inf <= 1e-8, (op, n, l2, inf)
     print(f"  iterations P_0 {its[0]}, P_n {its[1]}", flush=True)
     assert sum(its[1]) <= 1.5 * sum(its[0])
 
