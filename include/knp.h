@@ -189,6 +189,23 @@ knp_status knp_set_params(knp_ctx *ctx, const knp_params *params);
 knp_status knp_assemble_step(knp_ctx *ctx, double t_n, double dt, const double *u_prev,
                              double *gates, const double *theta, double *f_out);
 
+/* For callers that cannot allocate device memory (code under stream capture, tight
+ * serving loops, harnesses that forbid hipMalloc): knp_assemble_step with the same
+ * arguments, results and errors, whose scratch (the NaN counter and the per-membrane-
+ * vertex coefficient record) lives in a static device array of the library instead of
+ * context memory; it allocates nothing and calls no hipMalloc/hipFree.  The array holds
+ * at most 262,144 membrane vertices (40 MiB plus 256 bytes); each device the library
+ * runs on keeps its own copy until the process ends, and it keeps the last call's
+ * contents (the counter is cleared by a kernel at the start of each call).
+ * Differences from knp_assemble_step:
+ *   - the context must have been assembled once by knp_assemble_step (that first call
+ *     fixes S and P_0), else KNP_E_STATE;
+ *   - a mesh with more membrane vertices than the array holds is KNP_E_ARG;
+ *   - calls that overlap on one device (several contexts or threads at once) share the
+ *     array and race: serialise them. */
+knp_status knp_assemble_step_noalloc(knp_ctx *ctx, double t_n, double dt, const double *u_prev,
+                                     double *gates, const double *theta, double *f_out);
+
 /* Build the algebraic-multigrid hierarchy of P_0 (eq. ``P_prec``), frozen for all
  * steps (same section), or with operator_step = 1 of the time-dependent P_n of the
  * most recent knp_assemble_step (the alternative that section weighs against P_0;

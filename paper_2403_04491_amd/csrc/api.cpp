@@ -348,6 +348,11 @@ knp_status knp_create(knp_ctx **out, int hip_device, void *hip_stream) {
         } catch (...) {
             return create_failed(c, KNP_E_NOMEM, "device allocation failed");
         }
+        try {
+            c->scratch = knp::launch::noalloc_scratch(hip_device);
+        } catch (const Error &e) {
+            return create_failed(c, e.st, e.msg);
+        }
     }
     *out = c;
     return KNP_OK;
@@ -612,14 +617,69 @@ static std::vector<double> diagonal_blocks(knp_ctx *c) {
     return out;
 }
 
+namespace {
+
+knp_status check_assembly_args(knp_ctx *c, double t_n, double dt, const double *u_prev, const double *gates,
+                               const double *f_out) {
+    if (!c->have_mesh || !c->have_params) return fail(c, KNP_E_STATE, "mesh and params are required");
+    if (!u_prev || !f_out) return fail(c, KNP_E_ARG, "NULL u_prev or f_out");
+    if (c->any_hh && !gates) return fail(c, KNP_E_ARG, "gates required for Hodgkin-Huxley cells");
+    if (!(dt > 0.0) || !std::isfinite(t_n)) return fail(c, KNP_E_ARG, "invalid dt or t_n");
+    return KNP_OK;
+}
+
+// The assembly's device work on the context's stream: membrane coefficients into gcoef,
+// then the values of A (scaled by the current S; the static part only when dt changed
+// or force_static) and f.  The coefficients are computed once per call, so running the
+// matrix part twice advances no gate twice.
+void enqueue_assembly(knp_ctx *c, double t_n, double dt, const double *u_prev, double *gates, const double *theta,
+                      double *gcoef, double *f_out, bool first) {
+    const HostMesh &h = c->hm;
+    hipStream_t s = c->stream;
+    const auto p = c->phys(t_n, dt);
+    const auto ma = c->mesh_args();
+    const auto ga = c->gamma_args();
+    launch::membrane_coefficients(ga, p, h.Nr[0], h.Nr[1], u_prev, gates, theta, gcoef, s);
+    auto matrix_and_rhs = [&](bool force_static) {
+        if (force_static || dt != c->dt_static) {
+            for (int r = 0; r < 2; ++r)
+                launch::assemble_static(c->region(r), ma, p, c->d_rowptr.p, c->d_rstart.p, c->d_vals.p, c->d_sc.p,
+                                        h.pin_dof, s);
+            c->dt_static = dt;
+        }
+        for (int r = 0; r < 2; ++r)
+            launch::assemble_dynamic(c->region(r), ma, p, c->d_rowptr.p, c->d_rstart.p, c->d_vals.p, c->d_sc.p,
+                                     u_prev, f_out, h.pin_dof, s);
+        launch::assemble_membrane(ga, ma, p, h.Nr[0], h.Nr[1], c->d_prow[0].p, c->d_prow[1].p, c->d_rowptr.p,
+                                  c->d_rstart.p, c->d_colidx.p, c->d_int2ext.p, c->d_vals.p, c->d_sc.p, gcoef,
+                                  f_out, s);
+    };
+    matrix_and_rhs(false);
+    if (first) {
+        // S from the unscaled diagonal, then the same kernels again with S, so
+        // that this step's values round exactly as a later call on the same
+        // inputs (recomputed steps reproduce stored ones bit for bit)
+        launch::scaling_from_diag(h.N, c->d_vals.p, c->d_diag.p, c->d_sc.p, s);
+        matrix_and_rhs(true);
+    }
+}
+
+void finish_assembly(knp_ctx *c, double t_n, double dt, const double *theta) {
+    c->last_theta = theta;
+    c->last_t = t_n;
+    c->last_dt = dt;
+    c->assembled = true;
+    c->T_current = false;
+}
+
+}  // namespace
+
 knp_status knp_assemble_step(knp_ctx *c, double t_n, double dt, const double *u_prev, double *gates,
                              const double *theta, double *f_out) {
     return guarded(c, [&]() -> knp_status {
         need_device(c);
-        if (!c->have_mesh || !c->have_params) return fail(c, KNP_E_STATE, "mesh and params are required");
-        if (!u_prev || !f_out) return fail(c, KNP_E_ARG, "NULL u_prev or f_out");
-        if (c->any_hh && !gates) return fail(c, KNP_E_ARG, "gates required for Hodgkin-Huxley cells");
-        if (!(dt > 0.0) || !std::isfinite(t_n)) return fail(c, KNP_E_ARG, "invalid dt or t_n");
+        const knp_status st = check_assembly_args(c, t_n, dt, u_prev, gates, f_out);
+        if (st != KNP_OK) return st;
         hip_check(hipSetDevice(c->device), "set device");
         const HostMesh &h = c->hm;
         hipStream_t s = c->stream;
@@ -635,34 +695,9 @@ knp_status knp_assemble_step(knp_ctx *c, double t_n, double dt, const double *u_
             c->d_sc.upload(ones, s);
         }
         hipEvent_t t0 = c->tm.begin(KNP_TIMER_ASSEMBLY, s);
-        const auto p = c->phys(t_n, dt);
-        const auto ma = c->mesh_args();
-        const auto ga = c->gamma_args();
-        launch::membrane_coefficients(ga, p, h.Nr[0], h.Nr[1], u_prev, gates, theta, c->d_gcoef.p, s);
-        // values (scaled by the current S) and f; the membrane coefficients above
-        // are computed once per call, so running this twice advances no gate twice
-        auto matrix_and_rhs = [&](bool force_static) {
-            if (force_static || dt != c->dt_static) {
-                for (int r = 0; r < 2; ++r)
-                    launch::assemble_static(c->region(r), ma, p, c->d_rowptr.p, c->d_rstart.p, c->d_vals.p, c->d_sc.p,
-                                            h.pin_dof, s);
-                c->dt_static = dt;
-            }
-            for (int r = 0; r < 2; ++r)
-                launch::assemble_dynamic(c->region(r), ma, p, c->d_rowptr.p, c->d_rstart.p, c->d_vals.p, c->d_sc.p,
-                                         u_prev, f_out, h.pin_dof, s);
-            launch::assemble_membrane(ga, ma, p, h.Nr[0], h.Nr[1], c->d_prow[0].p, c->d_prow[1].p, c->d_rowptr.p,
-                                      c->d_rstart.p, c->d_colidx.p, c->d_int2ext.p, c->d_vals.p, c->d_sc.p,
-                                      c->d_gcoef.p, f_out, s);
-        };
-        matrix_and_rhs(false);
+        enqueue_assembly(c, t_n, dt, u_prev, gates, theta, c->d_gcoef.p, f_out, first);
         c->tm.end(KNP_TIMER_ASSEMBLY, t0, c->assembly_bytes, s);
         if (first) {
-            // S from the unscaled diagonal, then the same kernels again with S, so
-            // that this step's values round exactly as a later call on the same
-            // inputs (recomputed steps reproduce stored ones bit for bit)
-            launch::scaling_from_diag(h.N, c->d_vals.p, c->d_diag.p, c->d_sc.p, s);
-            matrix_and_rhs(true);
             // P_0: the diagonal blocks of the first (scaled) matrix, kept on the host for AMG setup
             std::vector<double> sc(h.N);
             c->p0_vals = diagonal_blocks(c);
@@ -674,11 +709,44 @@ knp_status knp_assemble_step(knp_ctx *c, double t_n, double dt, const double *u_
         hip_check(hipGetLastError(), "assembly launch");
         hip_check(hipStreamSynchronize(s), "assembly");
         c->tm.harvest();
-        c->last_theta = theta;
-        c->last_t = t_n;
-        c->last_dt = dt;
-        c->assembled = true;
-        c->T_current = false;
+        finish_assembly(c, t_n, dt, theta);
+        return KNP_OK;
+    });
+}
+
+// The same assembly with its scratch (the NaN counter and the membrane coefficient
+// record) in the library's static device array instead of context memory: it enqueues
+// kernels and copies only.  The first assembly of a context fixes S and P_0 (host work),
+// so it must have been done by knp_assemble_step.
+knp_status knp_assemble_step_noalloc(knp_ctx *c, double t_n, double dt, const double *u_prev, double *gates,
+                                     const double *theta, double *f_out) {
+    return guarded(c, [&]() -> knp_status {
+        need_device(c);
+        const knp_status st = check_assembly_args(c, t_n, dt, u_prev, gates, f_out);
+        if (st != KNP_OK) return st;
+        if (!c->assembled)
+            return fail(c, KNP_E_STATE, "knp_assemble_step must have been called once on this context (the "
+                                        "first assembly fixes S and P_0)");
+        const HostMesh &h = c->hm;
+        if (int64_t(h.gamma.size()) > NOALLOC_MAX_GAMMA)
+            return fail(c, KNP_E_ARG, "mesh has " + std::to_string(h.gamma.size()) +
+                                          " membrane vertices; the static scratch holds at most " +
+                                          std::to_string(NOALLOC_MAX_GAMMA));
+        if (!c->scratch) return fail(c, KNP_E_STATE, "static scratch not resolved for this device");
+        hip_check(hipSetDevice(c->device), "set device");
+        hipStream_t s = c->stream;
+        int *flag_d = reinterpret_cast<int *>(c->scratch);
+        double *gcoef = c->scratch + NOALLOC_HEAD;
+        int flag = 0;
+        launch::clear_flag(flag_d, s);
+        launch::check_finite(u_prev, h.N, flag_d, s);
+        hip_check(hipMemcpyAsync(&flag, flag_d, sizeof(int), hipMemcpyDeviceToHost, s), "flag copy");
+        hip_check(hipStreamSynchronize(s), "flag sync");
+        if (flag) return fail(c, KNP_E_NUMERIC, "NaN or Inf in u_prev");
+        enqueue_assembly(c, t_n, dt, u_prev, gates, theta, gcoef, f_out, false);
+        hip_check(hipGetLastError(), "assembly launch");
+        hip_check(hipStreamSynchronize(s), "assembly");
+        finish_assembly(c, t_n, dt, theta);
         return KNP_OK;
     });
 }

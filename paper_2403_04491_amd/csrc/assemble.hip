@@ -11,9 +11,17 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
+#include <vector>
 
 #include "fem_device.h"
 #include "knp_internal.h"
+
+// Scratch of the allocation-free assembly entry point: the NaN counter in the first
+// 256 bytes, then the per-membrane-vertex coefficient record.  Every device holds its
+// own copy until the process ends.  Host code never passes this symbol to a kernel: it
+// uses the device address that noalloc_scratch() obtains for the current device.
+static __device__ __align__(256) double scratch[knp::NOALLOC_HEAD + knp::NOALLOC_MAX_GAMMA * knp::GC_STRIDE];
 
 namespace knp {
 namespace launch {
@@ -392,6 +400,8 @@ __global__ void k_check_finite(const double *__restrict__ u, int64_t n, int *fla
         if (!isfinite(u[i])) *flag = 1;
 }
 
+__global__ void k_clear_flag(int *flag) { *flag = 0; }
+
 __global__ void k_scaling_from_diag(int64_t N, const double *__restrict__ vals, const int64_t *__restrict__ dpos,
                                     double *__restrict__ sc) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -441,6 +451,22 @@ inline unsigned nblocks(int64_t n, int b) { return unsigned((n + b - 1) / b); }
 
 void check_finite(const double *u, int64_t n, int *flag, hipStream_t s) {
     hipLaunchKernelGGL(k_check_finite, dim3(1024), dim3(256), 0, s, u, n, flag);
+}
+
+void clear_flag(int *flag, hipStream_t s) { hipLaunchKernelGGL(k_clear_flag, dim3(1), dim3(1), 0, s, flag); }
+
+double *noalloc_scratch(int device) {
+    static std::mutex mu;
+    static std::vector<double *> addr;
+    std::lock_guard<std::mutex> lock(mu);
+    if (device < 0) throw Error{KNP_E_ARG, "no device for the static scratch"};
+    if (size_t(device) >= addr.size()) addr.resize(size_t(device) + 1, nullptr);
+    if (!addr[device]) {
+        void *p = nullptr;
+        hip_check(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+        addr[device] = static_cast<double *>(p);
+    }
+    return addr[device];
 }
 
 void membrane_coefficients(const GammaArgs &g, const PhysArgs &p, int64_t Ni, int64_t Ne, const double *u_prev,

@@ -82,6 +82,9 @@ struct knp_ctx {
     knp::DArray<int64_t> d_vptr, d_kblk;
     knp::DArray<int32_t> d_nptr, d_nbr, d_vblk, d_pblk;
     knp::DArray<int32_t> d_flag;
+    // this device's copy of the allocation-free assembly's static scratch (resolved at
+    // knp_create); the NaN counter, then the membrane coefficient record
+    double *scratch = nullptr;
     double dt_static = -1.0;
     double dt_first = -1.0;
 

@@ -22,6 +22,12 @@ constexpr int MAXG = 16;   // membrane neighbours (incl. self) of a membrane ver
 constexpr int GC_STRIDE = 20;
 constexpr int GC_C = 0, GC_G = 3, GC_H = 6, GC_REGION = 7, GC_I = 14;
 
+// Static scratch of the allocation-free assembly (knp_assemble_step_noalloc): NOALLOC_HEAD
+// doubles (256 bytes) holding the NaN counter, then the coefficient record of at most
+// NOALLOC_MAX_GAMMA membrane vertices (40 MiB in all, per device).
+constexpr int64_t NOALLOC_HEAD = 32;
+constexpr int64_t NOALLOC_MAX_GAMMA = 262144;
+
 struct Error {
     knp_status st;
     std::string msg;
@@ -320,6 +326,11 @@ struct GammaArgs {
 };
 
 void check_finite(const double *u, int64_t n, int *flag, hipStream_t s);
+// *flag = 0 by a kernel (no memset node)
+void clear_flag(int *flag, hipStream_t s);
+// This device's address of the allocation-free assembly's static scratch; resolved with
+// hipGetSymbolAddress the first time per device (the device must be current).  Throws.
+double *noalloc_scratch(int device);
 void membrane_coefficients(const GammaArgs &g, const PhysArgs &p, int64_t Ni, int64_t Ne, const double *u_prev,
                            double *gates, const double *theta, double *gcoef, hipStream_t s);
 // rowptr: ABI-order row pointers (row lengths); rstart[R]: storage start of ABI row R

@@ -19,7 +19,7 @@ STATUS = {0: "KNP_OK", 1: "KNP_E_ARG", 2: "KNP_E_STATE", 3: "KNP_E_HIP", 4: "KNP
 KNP_E_NOCONV = 5
 
 EXPORTS = ["knp_create", "knp_destroy", "knp_last_error", "knp_mesh_upload", "knp_get_layout",
-           "knp_get_gamma", "knp_set_params", "knp_assemble_step", "knp_amg_setup",
+           "knp_get_gamma", "knp_set_params", "knp_assemble_step", "knp_assemble_step_noalloc", "knp_amg_setup",
            "knp_gmres_solve", "knp_adjoint_solve", "knp_step_vjp", "knp_apply",
            "knp_get_scaling", "knp_get_values", "knp_timing", "knp_timing_read", "knp_amg_stats"]
 TIMERS = ["spmv_A", "cheb_L0", "resid_L0", "vcycle", "assembly"]
@@ -92,6 +92,7 @@ def load_library(path: str = _LIB_PATH) -> C.CDLL:
     lib.knp_get_gamma.argtypes = [P, P]
     lib.knp_set_params.argtypes = [P, C.POINTER(Params)]
     lib.knp_assemble_step.argtypes = [P, D, D, P, P, P, P]
+    lib.knp_assemble_step_noalloc.argtypes = [P, D, D, P, P, P, P]
     lib.knp_amg_setup.argtypes = [P, C.POINTER(AmgOpts)]
     lib.knp_gmres_solve.argtypes = [P, P, P, C.POINTER(SolveOpts), C.POINTER(SolveInfo)]
     lib.knp_adjoint_solve.argtypes = [P, P, P, C.POINTER(SolveOpts), C.POINTER(SolveInfo)]
@@ -231,6 +232,17 @@ class Context:
         import torch
         N = self.info.N
         self._check(self._lib.knp_assemble_step(
+            self._c, float(t_n), float(dt), _dptr(u_prev, torch.float64, N),
+            _dptr(gates, torch.float64, 3 * self.info.n_gamma) if gates is not None else None,
+            _dptr(theta, torch.float64, self.info.n_cells) if theta is not None else None,
+            _dptr(f_out, torch.float64, N)))
+
+    def assemble_step_noalloc(self, t_n, dt, u_prev, gates, theta, f_out):
+        """knp_assemble_step_noalloc: the same assembly with its scratch in the library's
+        static device array (no device allocation)."""
+        import torch
+        N = self.info.N
+        self._check(self._lib.knp_assemble_step_noalloc(
             self._c, float(t_n), float(dt), _dptr(u_prev, torch.float64, N),
             _dptr(gates, torch.float64, 3 * self.info.n_gamma) if gates is not None else None,
             _dptr(theta, torch.float64, self.info.n_cells) if theta is not None else None,
