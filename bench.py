@@ -318,10 +318,12 @@ def model_a_bench(args, log):
     # small kernels fewer; 30000 would exceed the coarsest solve's dense blocks)
     ma_amg = dict(amg_flags(args), coarse_max=args.ma_coarse_max)
 
+    order = args.ma_order
+
     def run(nx, membrane, n_steps, timed):
         case = model_a_evolution_case(nx=nx, membrane=membrane, n_steps=n_steps)
         s = KnpSolver(case, amg=amg_opts(precision=1, **ma_amg),
-                      solve=solve_opts(rtol=1e-6, restart=30, max_it=2000))
+                      solve=solve_opts(rtol=1e-6, restart=30, max_it=2000), order=order)
         ri, re = s.membrane_rows()
         trace = torch.empty((n_steps + 1, ri.numel()), dtype=torch.float64, device=s.dev)
         trace[0] = s.u[ri] - s.u[re]
@@ -383,7 +385,7 @@ def model_a_bench(args, log):
         m = min(args.ma_pn_steps, n_steps)
         case_n = model_a_evolution_case(nx=nx, membrane="hh", n_steps=m)
         sn = KnpSolver(case_n, amg=amg_opts(precision=1, operator_step=1, **ma_amg),
-                       solve=solve_opts(rtol=1e-6, restart=30, max_it=2000))
+                       solve=solve_opts(rtol=1e-6, restart=30, max_it=2000), order=order)
         its_n, t_n = [], []
         for n in range(1, m + 1):
             torch.cuda.synchronize()
@@ -404,6 +406,9 @@ def model_a_bench(args, log):
         from oracle.assemble import Assembler, initial_gates, initial_state
         from oracle.timeloop import step as oracle_step
         oc = model_a_evolution_case(nx=args.ma_cpu_nx, membrane="hh", n_steps=args.ma_cpu_steps)
+        if order == 2:
+            from oracle.p2 import p2_case
+            oc = p2_case(oc)
         asm = Assembler(oc)
         u, w = initial_state(oc, asm.lay), initial_gates(oc, asm.lay)
         ts = []
@@ -416,7 +421,7 @@ def model_a_bench(args, log):
         per = float(np.median(ts))
         cpu = {"value": round(1.0 / per, 4), "unit": "time steps/s", "cores": 1, "kind": "oracle",
                "sample": f"{args.ma_cpu_steps} oracle steps (assembly + SuperLU) of the same Model A case at "
-                         f"N_x={args.ma_cpu_nx}, N={asm.lay.N} unknowns; median s/step {per:.2f}"}
+                         f"N_x={args.ma_cpu_nx}, p={order}, N={asm.lay.N} unknowns; median s/step {per:.2f}"}
     out = {
         "metric": "Model A time evolution: time steps/s and GMRES iterations per step over 300 steps",
         "value": round(len(times) / times.sum(), 3),
@@ -425,7 +430,7 @@ def model_a_bench(args, log):
         "ms_per_step": round(1e3 * times.mean(), 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64 (AMG levels f32)", "data": "synthetic",
-        "config": {"workload": f"Model A, 2D unit square with one cell, N_x={nx}, N={s.info.N} unknowns, HH with "
+        "config": {"workload": f"Model A, 2D unit square with one cell, N_x={nx}, p={order}, N={s.info.N} unknowns, HH with "
                                f"the periodic Na stimulus on Gamma, uniform initial data, dt=0.1 ms, {n_steps} steps, "
                                f"FGMRES(30) + AMG(P_0) FP32 levels, rtol 1e-6",
                    "N": s.info.N, "nnz_A": s.info.nnz_A, "parallelism": "1 GPU", "amg": ma_amg},
@@ -441,6 +446,82 @@ def model_a_bench(args, log):
         "traces": traces,
         "roofline": roof,
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def config2_bench(args, log):
+    """The 3D Model A workload at its full size: [0,1]^3 um with one cell, 32^3 x 6 tets
+    (N = 149,900), Hodgkin-Huxley membrane with the stimulus, dt = 0.05 ms, 100 steps,
+    FGMRES(30) + AMG(P_0) at rtol 1e-6 (FP64 and FP32 levels).  Step 1 (with the AMG
+    setup) is untimed; steps 2..100 are timed together.  The first steps are compared
+    with the oracle's stored ones (tests/golden/cfg2_oracle_steps.npz) when present."""
+    import numpy as np
+    import torch
+    from knp_inputs import config_case
+    from paper_2403_04491_amd import KnpSolver, amg_opts, solve_opts
+
+    golden = os.path.join(ROOT, "tests", "golden", "cfg2_oracle_steps.npz")
+    ref = None
+    if os.path.exists(golden):
+        from oracle.assemble import initial_state
+        from oracle.mesh import build_layout
+        g = np.load(golden, allow_pickle=False)
+        c0 = config_case(2)
+        u = [initial_state(c0, build_layout(c0))]
+        for d in g["increments"]:
+            u.append(u[-1] + d.astype(np.float64))
+        ref = u
+    runs = {}
+    for prec in (0, 1):
+        name = "fp64" if prec == 0 else "fp32_amg"
+        case = config_case(2)
+        s = KnpSolver(case, amg=amg_opts(precision=prec, **amg_flags(args)),
+                      solve=solve_opts(rtol=1e-6, restart=30, max_it=4000))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info1 = s.step(opts=solve_opts(rtol=1e-6, restart=args.first_restart, max_it=4000))
+        torch.cuda.synchronize()
+        t_first = time.perf_counter() - t0
+        errs = {}
+        states = {1: s.u.cpu().numpy()} if ref is not None else {}
+        its = []
+        ri, re = s.membrane_rows()
+        phiM = []
+        if prec == 0:
+            s.ctx.timing(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for n in range(2, case.n_steps + 1):
+            its.append(s.step().its)
+            if ref is not None and n < len(ref):
+                states[n] = s.u.cpu().numpy()
+            if n % 5 == 0:
+                phiM.append(round(float((s.u[ri] - s.u[re]).mean()) * 1e3, 2))
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        timers = s.ctx.timing_read() if prec == 0 else None
+        s.ctx.timing(False)
+        if ref is not None:
+            for n, un in states.items():
+                errs[str(n)] = {"l2": block_errors(s.info, un, ref[n]), "elementwise": block_errors_inf(s.info, un, ref[n])}
+        runs[name] = {"steps_per_s": round((case.n_steps - 1) / el, 2), "ms_per_step": round(1e3 * el / (case.n_steps - 1), 3),
+                      "its_per_step": {"mean": round(float(np.mean(its)), 2), "max": int(max(its)), "min": int(min(its))},
+                      "first_step": {"its": info1.its, "s_with_setup": round(t_first, 3)},
+                      "phi_M_mean_mV_every_5_steps": phiM,
+                      "error_vs_stored_oracle_steps": errs or None}
+        if timers is not None:
+            runs[name]["kernel_gbs"] = {k: round(t["bytes"] / (t["total_ms"] * 1e-3) / 1e9, 1)
+                                        for k, t in timers.items() if t["launches"] and t["bytes"] > 0}
+        log(f"[{name}] {runs[name]}")
+    out = {
+        "metric": "time steps/s of the 3D Model A workload (100 steps, HH + stimulus), GMRES its/step",
+        "value": runs["fp64"]["steps_per_s"], "unit": "time steps/s", "n_gpus": 1, "steps": 99, "warmup": 1,
+        "ms_per_step": runs["fp64"]["ms_per_step"], "higher_is_better": True, "dtype": "f64",
+        "data": "synthetic", "vs_baseline": None,
+        "config": {"workload": "3D Model A: [0,1]^3 um, one cell [0.25,0.75]^3, 32^3 x 6 tets, N=149,900, "
+                               "Hodgkin-Huxley with the stimulus, dt=0.05 ms, 100 steps, FGMRES(30) rtol 1e-6"},
+        "by_precision": runs,
     }
     print(json.dumps(out), flush=True)
 
@@ -497,6 +578,14 @@ def adjoint_bench(args, log):
     rng = np.random.default_rng(4004)
     cells = sorted(int(c) for c in rng.choice(len(case.theta), size=min(args.fd_cells, len(case.theta)), replace=False))
     gmax = float(np.abs(g).max())
+    # the noise floor of J: the same forward sweep at the same tolerance with another
+    # restart length, whose solutions differ only within that tolerance
+    from paper_2403_04491_amd.adjoint import AdjointProblem as _AP
+    prob2 = _AP(case, every=args.adj_every, rtol=args.fd_rtol_fwd, adj_rtol=args.fd_rtol_adj,
+                restart=max(30, args.adj_restart // 2), max_it=8000)
+    J2, _ = prob2.forward(theta)
+    noise = abs(float(J2) - J)
+    log(f"  J = {J:.10e}; with restart {max(30, args.adj_restart // 2)}: {float(J2):.10e} (noise {noise / abs(J):.2e} of J)")
     fd = []
     for h in (1e-6, 1e-3):
         for c in cells:
@@ -508,7 +597,8 @@ def adjoint_bench(args, log):
             Jm, _ = prob.forward(torch.tensor(tm, dtype=torch.float64, device=dev))
             d = (float(Jp) - float(Jm)) / (2.0 * h * case.theta[c])
             fd.append({"h_rel": h, "cell": c, "fd": d, "adjoint": float(g[c]),
-                       "rel_err_vs_max": abs(d - g[c]) / gmax, "rel_err": abs(d - g[c]) / abs(g[c])})
+                       "rel_err_vs_max": abs(d - g[c]) / gmax, "rel_err": abs(d - g[c]) / abs(g[c]),
+                       "noise_error_bound_rel": noise / (2.0 * h * case.theta[c]) / abs(g[c])})
             log(f"  FD h={h:g} cell {c}: fd {d:.6e} adjoint {g[c]:.6e} rel err {abs(d - g[c]) / abs(g[c]):.2e}")
     steps_per_s = n_full / (t_fast["forward_s"] + t_fast["reverse_s"])
     out = {
@@ -526,7 +616,11 @@ def adjoint_bench(args, log):
         "check": {"steps": case.n_steps, "forward_rtol": args.fd_rtol_fwd, "adjoint_rtol": args.fd_rtol_adj,
                   **t_tight, "J": J, "gradient": [float(v) for v in g],
                   "gradient_rel_diff_at_timed_adjoint_rtol": float(np.abs(g_loose - g).max() / gmax),
-                  "central_differences": fd},
+                  "J_noise_rel": noise / abs(J),
+                  "central_differences": fd,
+                  "central_differences_note": "noise_error_bound_rel = |J - J'| / (2 h theta_c |g_c|), J' the same "
+                                              "forward sweep with another restart length: a central difference "
+                                              "cannot resolve the gradient to better than this"},
     }
     print(json.dumps(out), flush=True)
 
@@ -688,9 +782,13 @@ def main():
     ap.add_argument("--large-steps", type=int, default=9)
     ap.add_argument("--large-first-restart", type=int, default=60)
     ap.add_argument("--fd-steps", type=int, default=4, help="horizon of the finite-difference check")
+    ap.add_argument("--config2", action="store_true",
+                    help="the 3D Model A workload at N_x = 32 (100 steps, HH + stimulus) instead of the lattice")
     ap.add_argument("--model-a", action="store_true",
                     help="Model A's time evolution (2D, N_x = 512, 300 steps) instead of the step throughput")
     ap.add_argument("--ma-nx", type=int, default=512)
+    ap.add_argument("--ma-order", type=int, default=1, choices=[1, 2],
+                    help="element order of the Model A workload (2: P2, N = 4.2e6 at N_x = 512)")
     ap.add_argument("--ma-steps", type=int, default=300)
     ap.add_argument("--ma-trace-nx", type=int, default=64, help="0 skips the three membrane traces")
     ap.add_argument("--ma-coarse-max", type=int, default=8000, help="AMG coarse_max of the Model A workload")
@@ -717,6 +815,9 @@ def main():
         return
     if args.model_a:
         model_a_bench(args, log)
+        return
+    if args.config2:
+        config2_bench(args, log)
         return
     if args.large:
         large_bench(args, log)

@@ -149,12 +149,35 @@ const char *knp_last_error(const knp_ctx *ctx);
  * is pinned to 0.  Builds the DOF maps and the structural CSR pattern of A on
  * the host and uploads them once.  Errors (KNP_E_ARG): dim not 2 or 3, indices
  * out of range, two cells touching, a cell touching the outer boundary, a pin
- * on the membrane, a vertex whose degree exceeds the assembly kernel's limit.
+ * on the membrane.  Any vertex degree is accepted: meshes whose vertices all have at
+ * most 32 region neighbours and 16 membrane neighbours use the element-walk kernels,
+ * others the product-form assembly of knp_mesh_upload_p2 with linear elements.
  * May be called once per context. */
 knp_status knp_mesh_upload(knp_ctx *ctx, int dim, int64_t n_vert, const double *xyz,
                            int64_t n_elem, const int32_t *elem_vert,
                            const int32_t *elem_tag, int64_t pin_vertex,
                            knp_mesh_info *out);
+
+/* The same with quadratic (P2) Lagrange elements (Sec. "Spatial discretization": elements
+ * of degree p; the robustness study and Model D (ii) use p = 2).  Arguments as for
+ * knp_mesh_upload: the vertex mesh, d + 1 vertices per element.  The library adds one node
+ * per edge: the edge (a, b), a < b, e-th in lexicographic order of its vertex pair, is
+ * node n_vert + e at the edge midpoint; membrane nodes (vertices and edges of membrane
+ * facets) get one copy per region.  Everywhere after this call "vertex" means node:
+ * knp_mesh_info.n_vert counts nodes (N = 4 (N_i + N_e) over nodes), knp_get_layout's
+ * dof_vertex and knp_get_gamma give node ids, the gates array has one row per membrane
+ * node, and the nonlinear membrane coefficients are P2 fields given by their values at
+ * the membrane nodes.  Element node order: the d + 1 vertices, then the edges in
+ * lexicographic order of the local pair; facets likewise.  knp_step_vjp stays order 1
+ * (KNP_E_ARG on such a context).  Other errors as knp_mesh_upload. */
+knp_status knp_mesh_upload_p2(knp_ctx *ctx, int dim, int64_t n_vert, const double *xyz, int64_t n_elem,
+                              const int32_t *elem_vert, const int32_t *elem_tag, int64_t pin_vertex,
+                              knp_mesh_info *out);
+
+/* The edge nodes of a P2 mesh: *n_edges (may be NULL) receives their number, and
+ * edge_vertices (host [2 * n_edges], may be NULL) the two vertices of node n_vert + e.
+ * Zero edges for an order-1 mesh. */
+knp_status knp_get_edges(knp_ctx *ctx, int64_t *n_edges, int32_t *edge_vertices);
 
 /* Host copies of the structural pattern and DOF maps for bit-exact checks:
  * rowptr [N+1] (int64), colidx [nnz_A] (int32, strictly ascending per row),

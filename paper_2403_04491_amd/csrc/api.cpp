@@ -316,6 +316,55 @@ void build_vertex_view(knp_ctx *c, const std::vector<int32_t> &cols) {
 extern "C" {
 
 // Text of the last failed knp_create on this thread (no context exists to hold it).
+// the product-form path (order 2, or order 1 beyond the element-walk kernels' limits):
+// the static operators (p2.cpp) and the membrane adjacency, on the device
+static void upload_p2(knp_ctx *c) {
+    const HostMesh &h = c->hm;
+    hipStream_t s = c->stream;
+    P2Host o;
+    build_p2_operators(h, o);
+    for (int r = 0; r < 2; ++r) {
+        c->p2_nent[r] = h.prow[r][h.Nr[r]];
+        c->d_p2_wptr[r].alloc(o.wptr[r].size());
+        c->d_p2_wptr[r].upload(o.wptr[r], s);
+        c->d_p2_wnode[r].alloc(o.wnode[r].size());
+        c->d_p2_wnode[r].upload(o.wnode[r], s);
+        c->d_p2_wval[r].alloc(o.wval[r].size());
+        c->d_p2_wval[r].upload(o.wval[r], s);
+        c->d_p2_erow[r].alloc(o.erow[r].size());
+        c->d_p2_erow[r].upload(o.erow[r], s);
+        c->d_p2_sval[r].alloc(std::max<size_t>(1, o.sval[r].size()));
+        if (!o.sval[r].empty()) c->d_p2_sval[r].upload(o.sval[r], s);
+        c->d_p2_mval[r].alloc(std::max<size_t>(1, o.mval[r].size()));
+        if (!o.mval[r].empty()) c->d_p2_mval[r].upload(o.mval[r], s);
+        c->d_p2_rpos[r].alloc(o.rpos[r].size());
+        c->d_p2_rpos[r].upload(o.rpos[r], s);
+    }
+    c->p2_nmem = h.grow.empty() ? 0 : h.grow.back();
+    c->d_grow.alloc(h.grow.size());
+    c->d_grow.upload(h.grow, s);
+    c->d_gcol.alloc(std::max<size_t>(1, h.gcol.size()));
+    if (!h.gcol.empty()) c->d_gcol.upload(h.gcol, s);
+    c->d_p2_mrow.alloc(o.mrow.size());
+    c->d_p2_mrow.upload(o.mrow, s);
+    c->d_p2_mg.alloc(o.mg.size());
+    c->d_p2_mg.upload(o.mg, s);
+    c->d_p2_cptr.alloc(o.cptr.size());
+    c->d_p2_cptr.upload(o.cptr, s);
+    c->d_p2_cnode.alloc(o.cnode.size());
+    c->d_p2_cnode.upload(o.cnode, s);
+    c->d_p2_cval.alloc(o.cval.size());
+    c->d_p2_cval.upload(o.cval, s);
+    hip_check(hipStreamSynchronize(s), "P2 operator upload");
+    // algorithmic bytes of one order-2 assembly: the products' terms and row starts,
+    // entry rows and columns, M, the values and f written, u read; membrane terms
+    double b = 16.0 * double(h.N);
+    for (int r = 0; r < 2; ++r)
+        b += 12.0 * double(o.wnode[r].size()) + 56.0 * double(c->p2_nent[r]);
+    b += 12.0 * double(o.cnode.size()) + 2.0 * (8.0 * 8.0 + 8.0 * 3.0) * double(c->p2_nmem);
+    c->assembly_bytes = b;
+}
+
 static thread_local std::string g_create_err = "no error";
 
 static knp_status create_failed(knp_ctx *c, knp_status st, std::string msg) {
@@ -369,13 +418,13 @@ void knp_destroy(knp_ctx *c) {
 
 const char *knp_last_error(const knp_ctx *c) { return c ? c->err.c_str() : g_create_err.c_str(); }
 
-knp_status knp_mesh_upload(knp_ctx *c, int dim, int64_t n_vert, const double *xyz, int64_t n_elem,
-                           const int32_t *elem_vert, const int32_t *elem_tag, int64_t pin_vertex,
-                           knp_mesh_info *out) {
+static knp_status mesh_upload(knp_ctx *c, int order, int dim, int64_t n_vert, const double *xyz, int64_t n_elem,
+                              const int32_t *elem_vert, const int32_t *elem_tag, int64_t pin_vertex,
+                              knp_mesh_info *out) {
     return guarded(c, [&]() -> knp_status {
         if (c->have_mesh) return fail(c, KNP_E_STATE, "mesh already uploaded");
         HostMesh m;
-        build_host_mesh(m, dim, n_vert, xyz, n_elem, elem_vert, elem_tag, pin_vertex);
+        build_host_mesh(m, dim, order, n_vert, xyz, n_elem, elem_vert, elem_tag, pin_vertex);
         c->hm = std::move(m);
         HostMesh &h = c->hm;
         if (!c->host_only) {
@@ -493,10 +542,11 @@ knp_status knp_mesh_upload(knp_ctx *c, int dim, int64_t n_vert, const double *xy
             c->bh.alloc(h.N);
             c->yh.alloc(h.N);
             c->dscal.alloc(64);
-            // algorithmic bytes of one per-step assembly: u_prev and f, the
-            // per-step values (phi columns of every row), incidence lists,
-            // element connectivity and coordinates, each touched once
-            {
+            if (!h.walk) upload_p2(c);
+            // algorithmic bytes of one per-step order-1 assembly: u_prev and f, the
+            // per-step values (phi columns of every row), incidence lists, element
+            // connectivity and coordinates, each touched once
+            if (h.walk) {
                 double b = 16.0 * double(h.N);
                 for (int r = 0; r < 2; ++r) {
                     b += 8.0 * 4.0 * double(h.prow[r][h.Nr[r]]);
@@ -528,6 +578,29 @@ knp_status knp_mesh_upload(knp_ctx *c, int dim, int64_t n_vert, const double *xy
             out->dim = h.dim;
             out->pin_dof = h.pin_dof;
         }
+        return KNP_OK;
+    });
+}
+
+knp_status knp_mesh_upload(knp_ctx *c, int dim, int64_t n_vert, const double *xyz, int64_t n_elem,
+                           const int32_t *elem_vert, const int32_t *elem_tag, int64_t pin_vertex,
+                           knp_mesh_info *out) {
+    return mesh_upload(c, 1, dim, n_vert, xyz, n_elem, elem_vert, elem_tag, pin_vertex, out);
+}
+
+knp_status knp_mesh_upload_p2(knp_ctx *c, int dim, int64_t n_vert, const double *xyz, int64_t n_elem,
+                              const int32_t *elem_vert, const int32_t *elem_tag, int64_t pin_vertex,
+                              knp_mesh_info *out) {
+    return mesh_upload(c, 2, dim, n_vert, xyz, n_elem, elem_vert, elem_tag, pin_vertex, out);
+}
+
+knp_status knp_get_edges(knp_ctx *c, int64_t *n_edges, int32_t *edge_vertices) {
+    return guarded(c, [&]() -> knp_status {
+        if (!c->have_mesh) return fail(c, KNP_E_STATE, "no mesh");
+        const HostMesh &h = c->hm;
+        const int64_t ne = int64_t(h.edges.size() / 2);
+        if (n_edges) *n_edges = ne;
+        if (edge_vertices) std::copy(h.edges.begin(), h.edges.end(), edge_vertices);
         return KNP_OK;
     });
 }
@@ -640,6 +713,27 @@ void enqueue_assembly(knp_ctx *c, double t_n, double dt, const double *u_prev, d
     const auto ma = c->mesh_args();
     const auto ga = c->gamma_args();
     launch::membrane_coefficients(ga, p, h.Nr[0], h.Nr[1], u_prev, gates, theta, gcoef, s);
+    if (!h.walk) {   // product form: order 2, or order 1 beyond the walk kernels' limits
+        auto p2_matrix_and_rhs = [&](bool force_static) {
+            if (force_static || dt != c->dt_static) {
+                for (int r = 0; r < 2; ++r)
+                    launch::p2_static(c->region(r), c->p2_bulk(r), p, c->d_rowptr.p, c->d_rstart.p, c->d_vals.p,
+                                      c->d_sc.p, h.pin_dof, s);
+                c->dt_static = dt;
+            }
+            for (int r = 0; r < 2; ++r)
+                launch::p2_dynamic(c->region(r), c->p2_bulk(r), p, c->d_rowptr.p, c->d_rstart.p, c->d_vals.p,
+                                   c->d_sc.p, u_prev, f_out, h.pin_dof, s);
+            launch::p2_membrane(ga, c->region(0), c->region(1), c->p2_mem(), p, c->d_rowptr.p, c->d_rstart.p,
+                                c->d_vals.p, c->d_sc.p, gcoef, f_out, s);
+        };
+        p2_matrix_and_rhs(false);
+        if (first) {
+            launch::scaling_from_diag(h.N, c->d_vals.p, c->d_diag.p, c->d_sc.p, s);
+            p2_matrix_and_rhs(true);
+        }
+        return;
+    }
     auto matrix_and_rhs = [&](bool force_static) {
         if (force_static || dt != c->dt_static) {
             for (int r = 0; r < 2; ++r)
@@ -899,6 +993,7 @@ knp_status knp_step_vjp(knp_ctx *c, const double *u_prev, const double *u_n, con
                         double *u_prev_bar, double *theta_bar) {
     return guarded(c, [&]() -> knp_status {
         need_device(c);
+        if (c->have_mesh && c->hm.order != 1) return fail(c, KNP_E_ARG, "knp_step_vjp supports order-1 meshes only");
         if (!c->assembled) return fail(c, KNP_E_STATE, "knp_assemble_step of this step must come first");
         if (!u_prev || !u_n || !lambda_n || !u_prev_bar) return fail(c, KNP_E_ARG, "NULL vector");
         if (c->any_hh || c->any_kir)

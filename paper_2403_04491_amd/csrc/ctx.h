@@ -56,6 +56,11 @@ struct knp_ctx {
     knp::DArray<uint32_t> d_fpos[2];
     knp::DArray<int32_t> d_cell_model, d_cell_stim;
     knp::DArray<double> d_gcoef;
+    // order 2: the static P2 operators (knp::P2Host on the device) and the membrane adjacency
+    knp::DArray<int64_t> d_p2_wptr[2], d_p2_cptr, d_grow;
+    knp::DArray<int32_t> d_p2_wnode[2], d_p2_erow[2], d_p2_rpos[2], d_p2_mrow, d_p2_cnode, d_gcol;
+    knp::DArray<double> d_p2_wval[2], d_p2_sval[2], d_p2_mval[2], d_p2_mg, d_p2_cval;
+    int64_t p2_nent[2] = {0, 0}, p2_nmem = 0;
     knp::DArray<int64_t> d_cgrow;   // membrane vertices of each cell (CSR)
     knp::DArray<int32_t> d_cgcol;
     knp::DArray<double> d_thv;      // per membrane vertex theta adjoint (VJP scratch)
@@ -114,6 +119,31 @@ struct knp_ctx {
     knp::launch::MeshArgs mesh_args() const;
     knp::launch::GammaArgs gamma_args() const;
     knp::launch::PhysArgs phys(double t, double dt) const;
+    knp::launch::P2Bulk p2_bulk(int r) const {
+        knp::launch::P2Bulk b;
+        b.nent = p2_nent[r];
+        b.wptr = d_p2_wptr[r].p;
+        b.wnode = d_p2_wnode[r].p;
+        b.erow = d_p2_erow[r].p;
+        b.wval = d_p2_wval[r].p;
+        b.sval = d_p2_sval[r].p;
+        b.mval = d_p2_mval[r].p;
+        return b;
+    }
+    knp::launch::P2Mem p2_mem() const {
+        knp::launch::P2Mem m;
+        m.nmem = p2_nmem;
+        m.grow = d_grow.p;
+        m.cptr = d_p2_cptr.p;
+        m.gcol = d_gcol.p;
+        m.mrow = d_p2_mrow.p;
+        m.cnode = d_p2_cnode.p;
+        m.rpos_i = d_p2_rpos[0].p;
+        m.rpos_e = d_p2_rpos[1].p;
+        m.mg = d_p2_mg.p;
+        m.cval = d_p2_cval.p;
+        return m;
+    }
     knp::CsrView viewA() const {
         knp::CsrView v;
         v.nrows = hm.N;

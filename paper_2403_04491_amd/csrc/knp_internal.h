@@ -36,9 +36,21 @@ struct Error {
 // ----------------------------------------------------------------------------- host mesh
 struct HostMesh {
     int dim = 0;
+    // Element order p.  For p = 2 the "vertices" of everything below are the P2 nodes:
+    // the mesh vertices keep their ids, the edge (a, b), a < b, numbered in lexicographic
+    // order of its vertex pair as e, is node n_vert_p1 + e at the edge midpoint; elements
+    // list their d + 1 vertices and then their edges in lexicographic order of the local
+    // pair, facets their d vertices (ascending) and then their edges the same way.
+    int order = 1;
+    int nv_elem = 0, nv_facet = 0;  // nodes per element and per membrane facet
+    int64_t n_vert_p1 = 0;          // mesh vertices
+    // order 1: every vertex within MAXN region and MAXG membrane neighbours, so the
+    // element-walk kernels (packed positions) apply; otherwise the product-form path
+    bool walk = false;
+    std::vector<int32_t> edges;     // p = 2: [n_edges*2] vertex pairs of the edge nodes
     int64_t n_vert = 0, n_elem = 0;
     std::vector<double> xyz;        // [n_vert*dim]
-    std::vector<int32_t> elem;      // [n_elem*(dim+1)]
+    std::vector<int32_t> elem;      // [n_elem*nv_elem]
     std::vector<int32_t> tag;       // [n_elem]
     int32_t n_cells = 0;
     int64_t Nr[2] = {0, 0};
@@ -48,7 +60,7 @@ struct HostMesh {
     std::vector<int32_t> vcell;     // [n_vert] cell id of ICS vertices, 0 otherwise
     std::vector<int32_t> gamma;     // membrane vertices, ascending
     std::vector<int32_t> gidx;      // [n_vert] index into gamma or -1
-    std::vector<int32_t> facets;    // [n_f*dim] membrane facets (global ids, ascending per facet)
+    std::vector<int32_t> facets;    // [n_f*nv_facet] membrane facets (global ids, vertices ascending)
     int64_t n_facets = 0;
     // scalar pattern of each region (region-local indices, ascending)
     std::vector<int64_t> prow[2];
@@ -76,9 +88,36 @@ struct HostMesh {
     int64_t pin_vertex = 0, pin_dof = 0;
 };
 
-// Builds everything above from the raw mesh; throws Error.
-void build_host_mesh(HostMesh &m, int dim, int64_t n_vert, const double *xyz, int64_t n_elem,
+// Builds everything above from the raw mesh (elem: d + 1 vertices per element) for
+// element order 1 or 2; throws Error.  The packed incidence positions (ipos, fpos) exist
+// only where the element-walk kernels apply (walk); the slot (low bits) always.
+void build_host_mesh(HostMesh &m, int dim, int order, int64_t n_vert, const double *xyz, int64_t n_elem,
                      const int32_t *elem, const int32_t *tag, int64_t pin_vertex);
+
+// ----------------------------------------------------------------------------- P2 operators
+// Static operators of the order-2 assembly, built on the host once per mesh from the
+// element and facet integrals; every per-step value is then a sparse product with the
+// nodal concentrations or membrane coefficients.
+//   Bulk, per region r, on its scalar pattern (entry p = (row node j, column node q)):
+//     sval[p] = int grad phi_j . grad phi_q,  mval[p] = int phi_j phi_q,
+//     terms wptr[p]..wptr[p+1]: (wnode, wval) with wval = int phi_m grad phi_j . grad phi_q
+//     summed over the elements containing j and q, one term per weight node m
+//     (region-local), so that int c_h grad phi_j . grad phi_q = sum_t wval_t c(wnode_t).
+//   Membrane, per membrane node g and membrane neighbour a (entry e of grow/gcol):
+//     mg[e] = int_Gamma phi_g phi_a;  terms cptr[e]..cptr[e+1]: (cnode, cval), cnode the
+//     membrane index of a weight node c, cval = int_Gamma phi_g phi_a phi_c;
+//     rpos[r][e] = position of a in the region-r scalar row of g.
+struct P2Host {
+    std::vector<int32_t> mrow;      // [n_mem] membrane node of each membrane entry
+    std::vector<int64_t> wptr[2];
+    std::vector<int32_t> wnode[2], erow[2];
+    std::vector<double> wval[2], sval[2], mval[2];
+    std::vector<double> mg;
+    std::vector<int64_t> cptr;
+    std::vector<int32_t> cnode, rpos[2];
+    std::vector<double> cval;
+};
+void build_p2_operators(const HostMesh &m, P2Host &out);   // throws Error
 
 // ----------------------------------------------------------------------------- device buffer
 template <typename T>
@@ -324,6 +363,31 @@ struct GammaArgs {
     const int32_t *gidx;       // [n_vert]
     const int32_t *cell_model, *cell_stim;
 };
+
+// order-2 assembly: device views of the P2Host operators
+struct P2Bulk {
+    int64_t nent = 0;
+    const int64_t *wptr = nullptr;
+    const int32_t *wnode = nullptr, *erow = nullptr;
+    const double *wval = nullptr, *sval = nullptr, *mval = nullptr;
+};
+struct P2Mem {
+    int64_t nmem = 0;
+    const int64_t *grow = nullptr, *cptr = nullptr;
+    const int32_t *gcol = nullptr, *mrow = nullptr, *cnode = nullptr, *rpos_i = nullptr, *rpos_e = nullptr;
+    const double *mg = nullptr, *cval = nullptr;
+};
+// the dt-dependent static blocks of one region (c rows: M + tau_k A; phi row: z_k tau_k A)
+void p2_static(const RegionArgs &ra, const P2Bulk &b, const PhysArgs &p, const int64_t *rowptr, const int64_t *rstart,
+               double *vals, const double *sc, int64_t pin_dof, hipStream_t s);
+// the per-step bulk blocks and f of one region
+void p2_dynamic(const RegionArgs &ra, const P2Bulk &b, const PhysArgs &p, const int64_t *rowptr,
+                const int64_t *rstart, double *vals, const double *sc, const double *u_prev, double *f,
+                int64_t pin_dof, hipStream_t s);
+// the membrane blocks and terms of f of both regions, from the coefficient records
+void p2_membrane(const GammaArgs &g, const RegionArgs &ra_i, const RegionArgs &ra_e, const P2Mem &mm, const PhysArgs &p,
+                 const int64_t *rowptr, const int64_t *rstart, double *vals, const double *sc, const double *gcoef,
+                 double *f, hipStream_t s);
 
 void check_finite(const double *u, int64_t n, int *flag, hipStream_t s);
 // *flag = 0 by a kernel (no memset node)

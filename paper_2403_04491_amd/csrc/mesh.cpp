@@ -43,19 +43,19 @@ int find_pos(const int32_t *row, int n, int32_t key) {
 
 }  // namespace
 
-void build_host_mesh(HostMesh &m, int dim, int64_t n_vert, const double *xyz, int64_t n_elem,
-                     const int32_t *elem, const int32_t *tag, int64_t pin_vertex) {
+void build_host_mesh(HostMesh &m, int dim, int order, int64_t n_vert, const double *xyz, int64_t n_elem,
+                     const int32_t *elem_in, const int32_t *tag, int64_t pin_vertex) {
     if (dim != 2 && dim != 3) fail("dim must be 2 or 3");
+    if (order != 1 && order != 2) fail("element order must be 1 or 2");
     if (n_vert <= 0 || n_elem <= 0) fail("empty mesh");
     if (n_vert >= (int64_t(1) << 31) - 1) fail("too many vertices for int32 indices");
-    if (!xyz || !elem || !tag) fail("NULL mesh array");
+    if (!xyz || !elem_in || !tag) fail("NULL mesh array");
     const int d1 = dim + 1;
     m = HostMesh();
     m.dim = dim;
-    m.n_vert = n_vert;
+    m.order = order;
+    m.n_vert_p1 = n_vert;
     m.n_elem = n_elem;
-    m.xyz.assign(xyz, xyz + n_vert * dim);
-    m.elem.assign(elem, elem + n_elem * d1);
     m.tag.assign(tag, tag + n_elem);
 
     int32_t maxtag = 0;
@@ -63,23 +63,76 @@ void build_host_mesh(HostMesh &m, int dim, int64_t n_vert, const double *xyz, in
         if (tag[e] < 0) fail("negative element tag");
         maxtag = std::max(maxtag, tag[e]);
         for (int a = 0; a < d1; ++a) {
-            int32_t v = elem[e * d1 + a];
+            int32_t v = elem_in[e * d1 + a];
             if (v < 0 || v >= n_vert) fail("element vertex out of range");
             for (int b = 0; b < a; ++b)
-                if (elem[e * d1 + b] == v) fail("degenerate element (repeated vertex)");
+                if (elem_in[e * d1 + b] == v) fail("degenerate element (repeated vertex)");
         }
     }
     m.n_cells = maxtag;
 
+    // ---- nodes: the vertices, and for order 2 one node per edge (lexicographic)
+    const int npair = d1 * (d1 - 1) / 2;
+    std::vector<int64_t> ekeys;      // a * n_vert + b of the sorted edges (order 2)
+    if (order == 1) {
+        m.nv_elem = d1;
+        m.nv_facet = dim;
+        m.n_vert = n_vert;
+        m.xyz.assign(xyz, xyz + n_vert * dim);
+        m.elem.assign(elem_in, elem_in + n_elem * d1);
+    } else {
+        m.nv_elem = d1 + npair;
+        m.nv_facet = dim + dim * (dim - 1) / 2;
+        ekeys.reserve(size_t(n_elem) * npair);
+        for (int64_t e = 0; e < n_elem; ++e)
+            for (int i = 0; i < d1; ++i)
+                for (int j = i + 1; j < d1; ++j) {
+                    const int64_t a = std::min(elem_in[e * d1 + i], elem_in[e * d1 + j]);
+                    const int64_t b = std::max(elem_in[e * d1 + i], elem_in[e * d1 + j]);
+                    ekeys.push_back(a * n_vert + b);
+                }
+        std::sort(ekeys.begin(), ekeys.end());
+        ekeys.erase(std::unique(ekeys.begin(), ekeys.end()), ekeys.end());
+        const int64_t ne = int64_t(ekeys.size());
+        m.n_vert = n_vert + ne;
+        if (m.n_vert >= (int64_t(1) << 31) - 1) fail("too many nodes for int32 indices");
+        m.edges.resize(size_t(ne) * 2);
+        m.xyz.resize(size_t(m.n_vert) * dim);
+        std::copy(xyz, xyz + n_vert * dim, m.xyz.begin());
+        for (int64_t k = 0; k < ne; ++k) {
+            const int64_t a = ekeys[k] / n_vert, b = ekeys[k] % n_vert;
+            m.edges[2 * k] = int32_t(a);
+            m.edges[2 * k + 1] = int32_t(b);
+            for (int c = 0; c < dim; ++c) m.xyz[(n_vert + k) * dim + c] = 0.5 * (xyz[a * dim + c] + xyz[b * dim + c]);
+        }
+        m.elem.resize(size_t(n_elem) * m.nv_elem);
+#pragma omp parallel for schedule(static)
+        for (int64_t e = 0; e < n_elem; ++e) {
+            int32_t *o = &m.elem[e * m.nv_elem];
+            int c = 0;
+            for (int i = 0; i < d1; ++i) o[c++] = elem_in[e * d1 + i];
+            for (int i = 0; i < d1; ++i)
+                for (int j = i + 1; j < d1; ++j) {
+                    const int64_t a = std::min(elem_in[e * d1 + i], elem_in[e * d1 + j]);
+                    const int64_t b = std::max(elem_in[e * d1 + i], elem_in[e * d1 + j]);
+                    o[c++] = int32_t(n_vert + (std::lower_bound(ekeys.begin(), ekeys.end(), a * n_vert + b) - ekeys.begin()));
+                }
+        }
+    }
+    m.walk = order == 1;
+    const int nv = m.nv_elem, nf = m.nv_facet;
+    const int32_t *elem = m.elem.data();
+    const int64_t n_node = m.n_vert;
+
     // ---- region membership, cell of each ICS vertex
-    std::vector<uint8_t> in_r[2] = {std::vector<uint8_t>(n_vert, 0), std::vector<uint8_t>(n_vert, 0)};
-    m.vcell.assign(n_vert, 0);
+    std::vector<uint8_t> in_r[2] = {std::vector<uint8_t>(n_node, 0), std::vector<uint8_t>(n_node, 0)};
+    m.vcell.assign(n_node, 0);
     std::vector<uint8_t> cell_seen(maxtag + 1, 0);
     for (int64_t e = 0; e < n_elem; ++e) {
         int r = tag[e] >= 1 ? 0 : 1;
         cell_seen[tag[e]] = 1;
-        for (int a = 0; a < d1; ++a) {
-            int32_t v = elem[e * d1 + a];
+        for (int a = 0; a < nv; ++a) {
+            int32_t v = elem[e * nv + a];
             in_r[r][v] = 1;
             if (r == 0) {
                 if (m.vcell[v] == 0)
@@ -92,8 +145,8 @@ void build_host_mesh(HostMesh &m, int dim, int64_t n_vert, const double *xyz, in
     for (int c = 1; c <= maxtag; ++c)
         if (!cell_seen[c]) fail("cell tags must be 1..n_cells without gaps");
     for (int r = 0; r < 2; ++r) {
-        m.loc[r].assign(n_vert, -1);
-        for (int64_t v = 0; v < n_vert; ++v)
+        m.loc[r].assign(n_node, -1);
+        for (int64_t v = 0; v < n_node; ++v)
             if (in_r[r][v]) {
                 m.loc[r][v] = int32_t(m.verts[r].size());
                 m.verts[r].push_back(int32_t(v));
@@ -106,8 +159,8 @@ void build_host_mesh(HostMesh &m, int dim, int64_t n_vert, const double *xyz, in
     m.N = 4 * (m.Nr[0] + m.Nr[1]);
     if (m.N >= (int64_t(1) << 31) - 1) fail("too many unknowns for int32 column indices");
 
-    m.gidx.assign(n_vert, -1);
-    for (int64_t v = 0; v < n_vert; ++v)
+    m.gidx.assign(n_node, -1);
+    for (int64_t v = 0; v < n_node; ++v)
         if (in_r[0][v] && in_r[1][v]) {
             m.gidx[v] = int32_t(m.gamma.size());
             m.gamma.push_back(int32_t(v));
@@ -119,7 +172,7 @@ void build_host_mesh(HostMesh &m, int dim, int64_t n_vert, const double *xyz, in
     // ---- membrane facets: ICS boundary faces that are also faces of ECS elements
     std::vector<Face> fi, fe;
     for (int64_t e = 0; e < n_elem; ++e) {
-        const int32_t *ev = &elem[e * d1];
+        const int32_t *ev = &elem[e * nv];   // its d + 1 vertices come first
         if (tag[e] >= 1) {
             for (int a = 0; a < d1; ++a) fi.push_back(make_face(ev, d1, a, tag[e]));
         } else {
@@ -147,9 +200,21 @@ void build_host_mesh(HostMesh &m, int dim, int64_t n_vert, const double *xyz, in
         i = j;
     }
     m.n_facets = int64_t(gf.size());
-    m.facets.resize(gf.size() * dim);
-    for (size_t f = 0; f < gf.size(); ++f)
-        for (int a = 0; a < dim; ++a) m.facets[f * dim + a] = gf[f].v[a];
+    m.facets.resize(gf.size() * nf);
+    for (size_t f = 0; f < gf.size(); ++f) {
+        int32_t *o = &m.facets[f * nf];
+        for (int a = 0; a < dim; ++a) o[a] = gf[f].v[a];
+        if (order == 2) {
+            int c = dim;
+            for (int i = 0; i < dim; ++i)
+                for (int j = i + 1; j < dim; ++j) {
+                    const int64_t key = int64_t(gf[f].v[i]) * n_vert + gf[f].v[j];   // ascending pair
+                    const auto it = std::lower_bound(ekeys.begin(), ekeys.end(), key);
+                    if (it == ekeys.end() || *it != key) fail("internal: facet edge not among the element edges");
+                    o[c++] = int32_t(n_vert + (it - ekeys.begin()));
+                }
+        }
+    }
     fi.clear();
     fi.shrink_to_fit();
     fe.clear();
@@ -162,7 +227,7 @@ void build_host_mesh(HostMesh &m, int dim, int64_t n_vert, const double *xyz, in
         irow.assign(Nr + 1, 0);
         for (int64_t e = 0; e < n_elem; ++e) {
             if ((tag[e] >= 1) != (r == 0)) continue;
-            for (int a = 0; a < d1; ++a) irow[m.loc[r][elem[e * d1 + a]] + 1]++;
+            for (int a = 0; a < nv; ++a) irow[m.loc[r][elem[e * nv + a]] + 1]++;
         }
         for (int64_t j = 0; j < Nr; ++j) irow[j + 1] += irow[j];
         m.ielem[r].assign(irow[Nr], 0);
@@ -170,10 +235,10 @@ void build_host_mesh(HostMesh &m, int dim, int64_t n_vert, const double *xyz, in
         std::vector<int64_t> fill(irow.begin(), irow.end() - 1);
         for (int64_t e = 0; e < n_elem; ++e) {
             if ((tag[e] >= 1) != (r == 0)) continue;
-            for (int a = 0; a < d1; ++a) {
-                int32_t j = m.loc[r][elem[e * d1 + a]];
+            for (int a = 0; a < nv; ++a) {
+                int32_t j = m.loc[r][elem[e * nv + a]];
                 m.ielem[r][fill[j]] = int32_t(e);
-                m.ipos[r][fill[j]] = uint32_t(a);     // slot; positions added below
+                m.ipos[r][fill[j]] = uint32_t(a);     // slot; order 1: positions added below
                 fill[j]++;
             }
         }
@@ -188,8 +253,8 @@ void build_host_mesh(HostMesh &m, int dim, int64_t n_vert, const double *xyz, in
             for (int64_t j = 0; j < Nr; ++j) {
                 buf.clear();
                 for (int64_t t = irow[j]; t < irow[j + 1]; ++t) {
-                    const int32_t *ev = &elem[int64_t(m.ielem[r][t]) * d1];
-                    for (int a = 0; a < d1; ++a) buf.push_back(m.loc[r][ev[a]]);
+                    const int32_t *ev = &elem[int64_t(m.ielem[r][t]) * nv];
+                    for (int a = 0; a < nv; ++a) buf.push_back(m.loc[r][ev[a]]);
                 }
                 std::sort(buf.begin(), buf.end());
                 int64_t cnt = std::unique(buf.begin(), buf.end()) - buf.begin();
@@ -200,7 +265,7 @@ void build_host_mesh(HostMesh &m, int dim, int64_t n_vert, const double *xyz, in
                 prow[j + 1] = cnt;
             }
         }
-        if (bad) fail("a vertex has more region neighbours than the assembly kernel supports");
+        if (bad) m.walk = false;
         for (int64_t j = 0; j < Nr; ++j) prow[j + 1] += prow[j];
         m.pcol[r].assign(prow[Nr], 0);
 #pragma omp parallel
@@ -210,13 +275,14 @@ void build_host_mesh(HostMesh &m, int dim, int64_t n_vert, const double *xyz, in
             for (int64_t j = 0; j < Nr; ++j) {
                 buf.clear();
                 for (int64_t t = irow[j]; t < irow[j + 1]; ++t) {
-                    const int32_t *ev = &elem[int64_t(m.ielem[r][t]) * d1];
-                    for (int a = 0; a < d1; ++a) buf.push_back(m.loc[r][ev[a]]);
+                    const int32_t *ev = &elem[int64_t(m.ielem[r][t]) * nv];
+                    for (int a = 0; a < nv; ++a) buf.push_back(m.loc[r][ev[a]]);
                 }
                 std::sort(buf.begin(), buf.end());
                 int64_t cnt = std::unique(buf.begin(), buf.end()) - buf.begin();
                 int32_t *row = &m.pcol[r][prow[j]];
                 std::copy(buf.begin(), buf.begin() + cnt, row);
+                if (!m.walk) continue;
                 for (int64_t t = irow[j]; t < irow[j + 1]; ++t) {
                     const int32_t *ev = &elem[int64_t(m.ielem[r][t]) * d1];
                     uint32_t packed = m.ipos[r][t] & 3u;
@@ -234,14 +300,14 @@ void build_host_mesh(HostMesh &m, int dim, int64_t n_vert, const double *xyz, in
     const int64_t ng = int64_t(m.gamma.size());
     m.frow.assign(ng + 1, 0);
     for (int64_t f = 0; f < m.n_facets; ++f)
-        for (int a = 0; a < dim; ++a) m.frow[m.gidx[m.facets[f * dim + a]] + 1]++;
+        for (int a = 0; a < nf; ++a) m.frow[m.gidx[m.facets[f * nf + a]] + 1]++;
     for (int64_t g = 0; g < ng; ++g) m.frow[g + 1] += m.frow[g];
     m.ffacet.assign(m.frow[ng], 0);
     {
         std::vector<int64_t> fill(m.frow.begin(), m.frow.end() - 1);
         for (int64_t f = 0; f < m.n_facets; ++f)
-            for (int a = 0; a < dim; ++a) {
-                int32_t g = m.gidx[m.facets[f * dim + a]];
+            for (int a = 0; a < nf; ++a) {
+                int32_t g = m.gidx[m.facets[f * nf + a]];
                 m.ffacet[fill[g]++] = int32_t(f);
             }
     }
@@ -251,17 +317,17 @@ void build_host_mesh(HostMesh &m, int dim, int64_t n_vert, const double *xyz, in
     for (int64_t g = 0; g < ng; ++g) {
         std::vector<int32_t> &buf = gnb[g];
         for (int64_t t = m.frow[g]; t < m.frow[g + 1]; ++t)
-            for (int a = 0; a < dim; ++a) buf.push_back(m.facets[int64_t(m.ffacet[t]) * dim + a]);
+            for (int a = 0; a < nf; ++a) buf.push_back(m.facets[int64_t(m.ffacet[t]) * nf + a]);
         std::sort(buf.begin(), buf.end());
         buf.erase(std::unique(buf.begin(), buf.end()), buf.end());
         if (int(buf.size()) > MAXG) gbad = 1;
         m.grow[g + 1] = m.grow[g] + int64_t(buf.size());
     }
-    if (gbad) fail("a membrane vertex has more membrane neighbours than the assembly kernel supports");
+    if (gbad) m.walk = false;
     m.gcol.resize(m.grow[ng]);
     for (int64_t g = 0; g < ng; ++g) std::copy(gnb[g].begin(), gnb[g].end(), m.gcol.begin() + m.grow[g]);
     for (int r = 0; r < 2; ++r) m.fpos[r].assign(m.frow[ng], 0);
-    for (int64_t g = 0; g < ng; ++g) {
+    for (int64_t g = 0; g < ng && order == 1; ++g) {   // slots (order 1), positions (walk)
         const int32_t v = m.gamma[g];
         const int32_t *grow_p = &m.gcol[m.grow[g]];
         const int gn = int(m.grow[g + 1] - m.grow[g]);
@@ -275,7 +341,7 @@ void build_host_mesh(HostMesh &m, int dim, int64_t n_vert, const double *xyz, in
                 const int32_t *row = &m.pcol[r][m.prow[r][j]];
                 const int n = int(m.prow[r][j + 1] - m.prow[r][j]);
                 uint32_t packed = uint32_t(slot);
-                for (int a = 0; a < dim; ++a) {
+                for (int a = 0; a < dim && m.walk; ++a) {
                     int p = find_pos(row, n, m.loc[r][fv[a]]);
                     int pg = find_pos(grow_p, gn, fv[a]);
                     if (p < 0 || pg < 0) fail("internal: membrane facet outside the region pattern");

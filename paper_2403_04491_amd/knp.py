@@ -20,6 +20,7 @@ KNP_E_NOCONV = 5
 
 EXPORTS = ["knp_create", "knp_destroy", "knp_last_error", "knp_mesh_upload", "knp_get_layout",
            "knp_get_gamma", "knp_set_params", "knp_assemble_step", "knp_assemble_step_noalloc", "knp_amg_setup",
+           "knp_mesh_upload_p2", "knp_get_edges",
            "knp_gmres_solve", "knp_adjoint_solve", "knp_step_vjp", "knp_apply",
            "knp_get_scaling", "knp_get_values", "knp_timing", "knp_timing_read", "knp_amg_stats"]
 TIMERS = ["spmv_A", "cheb_L0", "resid_L0", "vcycle", "assembly"]
@@ -88,6 +89,8 @@ def load_library(path: str = _LIB_PATH) -> C.CDLL:
     lib.knp_last_error.argtypes = [P]
     lib.knp_last_error.restype = C.c_char_p
     lib.knp_mesh_upload.argtypes = [P, C.c_int, I64, P, I64, P, P, I64, C.POINTER(MeshInfo)]
+    lib.knp_mesh_upload_p2.argtypes = [P, C.c_int, I64, P, I64, P, P, I64, C.POINTER(MeshInfo)]
+    lib.knp_get_edges.argtypes = [P, P, P]
     lib.knp_get_layout.argtypes = [P, P, P, P]
     lib.knp_get_gamma.argtypes = [P, P]
     lib.knp_set_params.argtypes = [P, C.POINTER(Params)]
@@ -184,15 +187,26 @@ class Context:
             pass
 
     # ------------------------------------------------------------------ setup
-    def mesh_upload(self, dim, xyz, elem, tag, pin_vertex=0) -> MeshInfo:
+    def mesh_upload(self, dim, xyz, elem, tag, pin_vertex=0, order=1) -> MeshInfo:
+        """knp_mesh_upload (order 1) or knp_mesh_upload_p2 (order 2): the vertex mesh."""
         xyz = np.ascontiguousarray(xyz, dtype=np.float64)
         elem = np.ascontiguousarray(elem, dtype=np.int32)
         tag = np.ascontiguousarray(tag, dtype=np.int32)
         info = MeshInfo()
-        self._check(self._lib.knp_mesh_upload(self._c, dim, xyz.shape[0], _hptr(xyz), elem.shape[0],
-                                              _hptr(elem), _hptr(tag), int(pin_vertex), C.byref(info)))
+        fn = {1: self._lib.knp_mesh_upload, 2: self._lib.knp_mesh_upload_p2}[order]
+        self._check(fn(self._c, dim, xyz.shape[0], _hptr(xyz), elem.shape[0], _hptr(elem), _hptr(tag),
+                       int(pin_vertex), C.byref(info)))
         self.info = info
         return info
+
+    def get_edges(self):
+        """[n_edges, 2] vertex pairs of the edge nodes (node n_vert + e) of an order-2 mesh."""
+        n = C.c_int64(0)
+        self._check(self._lib.knp_get_edges(self._c, C.byref(n), None))
+        out = np.empty((n.value, 2), np.int32)
+        if n.value:
+            self._check(self._lib.knp_get_edges(self._c, None, _hptr(out)))
+        return out
 
     def get_layout(self):
         N, nnz = self.info.N, self.info.nnz_A

@@ -9,30 +9,38 @@ import torch
 from .knp import Context, amg_opts, solve_opts
 
 
-def initial_vector(case, dof_vertex, info):
-    """u_0 in the library's DOF layout from per-vertex initial data."""
+def initial_vector(case, dof_vertex, info, edges=None):
+    """u_0 in the library's DOF layout from per-vertex initial data.  With the edge list of
+    an order-2 mesh, the data at the edge node n_vert + e is the mean of its two vertices'
+    (the linear interpolant of the per-vertex data)."""
+    conc = case.conc0
+    if edges is not None and len(edges):
+        conc = np.concatenate([conc, 0.5 * (conc[:, :, edges[:, 0]] + conc[:, :, edges[:, 1]])], axis=2)
     u0 = np.empty(info.N)
     Nr = (info.N_i, info.N_e)
     off = (0, 4 * info.N_i)
     for r in (0, 1):
         for f in range(4):
             sl = slice(off[r] + f * Nr[r], off[r] + (f + 1) * Nr[r])
-            u0[sl] = case.conc0[r, f, dof_vertex[sl]] if f < 3 else case.phi0[r]
+            u0[sl] = conc[r, f, dof_vertex[sl]] if f < 3 else case.phi0[r]
     return u0
 
 
 class KnpSolver:
     """Holds one context and the state (u, gates) of a run on one GPU."""
 
-    def __init__(self, case, device=0, amg=None, solve=None, theta=None):
+    def __init__(self, case, device=0, amg=None, solve=None, theta=None, order=1):
+        """case: a vertex mesh with per-vertex data; order 2 adds the edge nodes (P2)."""
         self.case = case
+        self.order = order
         self.dev = torch.device("cuda", device)
         self.ctx = Context(device)
-        self.info = self.ctx.mesh_upload(case.dim, case.xyz, case.elem, case.tag, case.pin_vertex)
+        self.info = self.ctx.mesh_upload(case.dim, case.xyz, case.elem, case.tag, case.pin_vertex, order=order)
         self.ctx.set_params(case.params, case.cell_model, case.cell_stim)
         self.rowptr, self.colidx, self.dof_vertex = self.ctx.get_layout()
         self.gamma = self.ctx.get_gamma()
-        u0 = initial_vector(case, self.dof_vertex, self.info)
+        self.edges = self.ctx.get_edges() if order == 2 else None
+        u0 = initial_vector(case, self.dof_vertex, self.info, self.edges)
         self.u = torch.tensor(u0, dtype=torch.float64, device=self.dev)
         g0 = np.tile(np.asarray(case.params["gates0"], dtype=np.float64), (self.info.n_gamma, 1))
         self.gates = torch.tensor(g0, dtype=torch.float64, device=self.dev).contiguous()
@@ -46,11 +54,13 @@ class KnpSolver:
         self.history = []
 
     def membrane_rows(self):
-        """Device indices (phi_i rows, phi_e rows) of the membrane vertices, in the
-        order of knp_get_gamma, so that phi_M = u[rows_i] - u[rows_e]."""
+        """Device indices (phi_i rows, phi_e rows) of the membrane nodes (vertices, and
+        edge nodes n_vert + e at order 2), in the order of knp_get_gamma, so that
+        phi_M = u[rows_i] - u[rows_e]."""
         Ni, Ne = self.info.N_i, self.info.N_e
-        pos_i = np.full(self.case.n_vert, -1, np.int64)
-        pos_e = np.full(self.case.n_vert, -1, np.int64)
+        n_nodes = self.case.n_vert + (len(self.edges) if self.edges is not None else 0)
+        pos_i = np.full(n_nodes, -1, np.int64)
+        pos_e = np.full(n_nodes, -1, np.int64)
         pos_i[self.dof_vertex[3 * Ni:4 * Ni]] = np.arange(3 * Ni, 4 * Ni)
         pos_e[self.dof_vertex[4 * Ni + 3 * Ne:]] = np.arange(4 * Ni + 3 * Ne, 4 * Ni + 4 * Ne)
         ri, re = pos_i[self.gamma], pos_e[self.gamma]

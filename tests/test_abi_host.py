@@ -17,7 +17,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def test_library_exports_every_declared_symbol():
     header = open(os.path.join(ROOT, "include", "knp.h")).read()
-    declared = set(re.findall(r"\b(knp_[a-z_]+)\s*\(", header))
+    declared = set(re.findall(r"\b(knp_[a-z0-9_]+)\s*\(", header))
     assert declared == set(knp.EXPORTS)
     lib = ctypes.CDLL(knp._LIB_PATH)
     for name in declared:
@@ -29,6 +29,7 @@ CASES = {
     "modelA3d_nx8_hh": lambda: model_a_case(3, 8, "hh", 5e-5, 1),
     "lattice4_pp5": lambda: config_case(3, per_pitch=5),
     "lattice2_pp6_theta": lambda: config_case(4, per_pitch=6),
+    "fan40": lambda: __import__("knp_inputs.fan", fromlist=["fan_case"]).fan_case(),
 }
 
 
@@ -52,6 +53,30 @@ def test_host_layout_bit_exact(name):
     # nnz(P_0) = 4 sum_r P_r
     from oracle.mesh import region_pairs
     assert info.nnz_P0 == 4 * sum(len(region_pairs(case, lay, r)) for r in (0, 1))
+
+
+@pytest.mark.parametrize("d,nx,membrane", [(2, 4, "leak"), (2, 8, "hh"), (3, 4, "hh")])
+def test_host_layout_bit_exact_p2(d, nx, membrane):
+    """Quadratic elements: node numbering (edges lexicographic after the vertices), DOF
+    numbering, membrane nodes and the structural pattern equal the oracle's P2 layout."""
+    from oracle.p2 import p2_case
+    base = model_a_case(d, nx, membrane, 1e-4, 1)
+    case = p2_case(base)
+    ctx = knp.Context(-1)
+    info = ctx.mesh_upload(base.dim, base.xyz, base.elem, base.tag, base.pin_vertex, order=2)
+    rowptr, colidx, dofv = ctx.get_layout()
+    lay = build_layout(case)
+    rp, ci = structural_pattern(case, lay)
+    assert info.n_vert == case.n_vert
+    assert (info.N_i, info.N_e, info.N) == (lay.N_r[0], lay.N_r[1], lay.N)
+    assert info.n_gamma == len(lay.gamma) and info.n_facets == len(lay.facets)
+    assert info.pin_dof == lay.pin_dof
+    assert np.array_equal(rowptr, rp)
+    assert np.array_equal(colidx, ci)
+    exp_v = np.concatenate([np.tile(lay.verts[0], 4), np.tile(lay.verts[1], 4)])
+    assert np.array_equal(dofv, exp_v)
+    assert np.array_equal(ctx.get_gamma(), lay.gamma)
+    assert np.array_equal(ctx.get_edges(), case.edges)
 
 
 def _expect_arg_error(case, tag=None, pin=0, elem=None):
