@@ -100,6 +100,8 @@ template struct DArray<float>;
 template struct DArray<int32_t>;
 template struct DArray<int64_t>;
 template struct DArray<uint32_t>;
+template struct DArray<uint8_t>;
+template struct DArray<RowGroup>;
 
 }  // namespace knp
 
@@ -316,6 +318,33 @@ void build_vertex_view(knp_ctx *c, const std::vector<int32_t> &cols) {
 extern "C" {
 
 // Text of the last failed knp_create on this thread (no context exists to hold it).
+// the membrane operators of the product form (p2.cpp) and the membrane adjacency, on the
+// device; returns their algorithmic bytes per assembly (terms, per-entry records, values)
+static double upload_p2_membrane(knp_ctx *c, const P2Host &o) {
+    const HostMesh &h = c->hm;
+    hipStream_t s = c->stream;
+    for (int r = 0; r < 2; ++r) {
+        c->d_p2_rpos[r].alloc(o.rpos[r].size());
+        c->d_p2_rpos[r].upload(o.rpos[r], s);
+    }
+    c->p2_nmem = h.grow.empty() ? 0 : h.grow.back();
+    c->d_grow.alloc(h.grow.size());
+    c->d_grow.upload(h.grow, s);
+    c->d_gcol.alloc(std::max<size_t>(1, h.gcol.size()));
+    if (!h.gcol.empty()) c->d_gcol.upload(h.gcol, s);
+    c->d_p2_mrow.alloc(o.mrow.size());
+    c->d_p2_mrow.upload(o.mrow, s);
+    c->d_p2_mg.alloc(o.mg.size());
+    c->d_p2_mg.upload(o.mg, s);
+    c->d_p2_cptr.alloc(o.cptr.size());
+    c->d_p2_cptr.upload(o.cptr, s);
+    c->d_p2_cnode.alloc(o.cnode.size());
+    c->d_p2_cnode.upload(o.cnode, s);
+    c->d_p2_cval.alloc(o.cval.size());
+    c->d_p2_cval.upload(o.cval, s);
+    return 12.0 * double(o.cnode.size()) + 2.0 * (8.0 * 8.0 + 8.0 * 3.0) * double(c->p2_nmem);
+}
+
 // the product-form path (order 2, or order 1 beyond the element-walk kernels' limits):
 // the static operators (p2.cpp) and the membrane adjacency, on the device
 static void upload_p2(knp_ctx *c) {
@@ -337,31 +366,51 @@ static void upload_p2(knp_ctx *c) {
         if (!o.sval[r].empty()) c->d_p2_sval[r].upload(o.sval[r], s);
         c->d_p2_mval[r].alloc(std::max<size_t>(1, o.mval[r].size()));
         if (!o.mval[r].empty()) c->d_p2_mval[r].upload(o.mval[r], s);
-        c->d_p2_rpos[r].alloc(o.rpos[r].size());
-        c->d_p2_rpos[r].upload(o.rpos[r], s);
     }
-    c->p2_nmem = h.grow.empty() ? 0 : h.grow.back();
-    c->d_grow.alloc(h.grow.size());
-    c->d_grow.upload(h.grow, s);
-    c->d_gcol.alloc(std::max<size_t>(1, h.gcol.size()));
-    if (!h.gcol.empty()) c->d_gcol.upload(h.gcol, s);
-    c->d_p2_mrow.alloc(o.mrow.size());
-    c->d_p2_mrow.upload(o.mrow, s);
-    c->d_p2_mg.alloc(o.mg.size());
-    c->d_p2_mg.upload(o.mg, s);
-    c->d_p2_cptr.alloc(o.cptr.size());
-    c->d_p2_cptr.upload(o.cptr, s);
-    c->d_p2_cnode.alloc(o.cnode.size());
-    c->d_p2_cnode.upload(o.cnode, s);
-    c->d_p2_cval.alloc(o.cval.size());
-    c->d_p2_cval.upload(o.cval, s);
+    const double bm = upload_p2_membrane(c, o);
     hip_check(hipStreamSynchronize(s), "P2 operator upload");
-    // algorithmic bytes of one order-2 assembly: the products' terms and row starts,
+    // algorithmic bytes of one product-form assembly: the products' terms and row starts,
     // entry rows and columns, M, the values and f written, u read; membrane terms
-    double b = 16.0 * double(h.N);
+    double b = 16.0 * double(h.N) + bm;
     for (int r = 0; r < 2; ++r)
         b += 12.0 * double(o.wnode[r].size()) + 56.0 * double(c->p2_nent[r]);
-    b += 12.0 * double(o.cnode.size()) + 2.0 * (8.0 * 8.0 + 8.0 * 3.0) * double(c->p2_nmem);
+    c->assembly_bytes = b;
+}
+
+// order 1 within the walk limits: the row terms of the per-step bulk values (rows.cpp)
+static void upload_rows(knp_ctx *c) {
+    const HostMesh &h = c->hm;
+    hipStream_t s = c->stream;
+    RowTerms rt[2];
+    if (!build_row_terms(h, rt)) throw Error{KNP_E_ARG, "internal: row longer than a row group"};
+    // algorithmic bytes of one per-step bulk assembly, each array touched once: u_prev,
+    // f and S; per region the groups, row pointers, and per row vertex the four rows'
+    // lengths and storage starts; per entry its column, term count, mass weight and the
+    // four values written; the terms (weight and position)
+    double b = 24.0 * double(h.N);
+    for (int r = 0; r < 2; ++r) {
+        const RowTerms &o = rt[r];
+        const int64_t nent = h.prow[r][h.Nr[r]];
+        c->rows_ngroups[r] = int64_t(o.groups.size()) - 1;
+        c->d_rgroups[r].alloc(o.groups.size());
+        c->d_rgroups[r].upload(o.groups, s);
+        c->d_rcount[r].alloc(o.tcount.size());
+        c->d_rcount[r].upload(o.tcount, s);
+        c->d_rslot[r].alloc(o.tslot.size());
+        c->d_rslot[r].upload(o.tslot, s);
+        c->d_rval[r].alloc(o.tval.size());
+        c->d_rval[r].upload(o.tval, s);
+        c->d_rmval[r].alloc(o.mval.size());
+        c->d_rmval[r].upload(o.mval, s);
+        b += 24.0 * double(o.groups.size()) + 8.0 * double(h.Nr[r] + 1) + 4.0 * 24.0 * double(h.Nr[r]);
+        b += (4.0 + 1.0 + 8.0 + 4.0 * 8.0) * double(nent) + 9.0 * double(o.groups.back().term0);
+    }
+    // the membrane blocks: the product form's membrane operators
+    P2Host o;
+    build_p2_membrane(h, o);
+    b += upload_p2_membrane(c, o);
+    hip_check(hipStreamSynchronize(s), "row term upload");
+    c->rows = true;
     c->assembly_bytes = b;
 }
 
@@ -543,18 +592,7 @@ static knp_status mesh_upload(knp_ctx *c, int order, int dim, int64_t n_vert, co
             c->yh.alloc(h.N);
             c->dscal.alloc(64);
             if (!h.walk) upload_p2(c);
-            // algorithmic bytes of one per-step order-1 assembly: u_prev and f, the
-            // per-step values (phi columns of every row), incidence lists, element
-            // connectivity and coordinates, each touched once
-            if (h.walk) {
-                double b = 16.0 * double(h.N);
-                for (int r = 0; r < 2; ++r) {
-                    b += 8.0 * 4.0 * double(h.prow[r][h.Nr[r]]);
-                    b += 8.0 * double(h.Nr[r] + 1) + 8.0 * double(h.irow[r][h.Nr[r]]);
-                }
-                b += 4.0 * double(h.elem.size()) + 8.0 * double(h.xyz.size());
-                c->assembly_bytes = b;
-            }
+            if (h.walk) upload_rows(c);
             // element and incidence data stay; host copies of the big incidence
             // arrays are no longer needed
             for (int r = 0; r < 2; ++r) {
@@ -742,11 +780,10 @@ void enqueue_assembly(knp_ctx *c, double t_n, double dt, const double *u_prev, d
             c->dt_static = dt;
         }
         for (int r = 0; r < 2; ++r)
-            launch::assemble_dynamic(c->region(r), ma, p, c->d_rowptr.p, c->d_rstart.p, c->d_vals.p, c->d_sc.p,
-                                     u_prev, f_out, h.pin_dof, s);
-        launch::assemble_membrane(ga, ma, p, h.Nr[0], h.Nr[1], c->d_prow[0].p, c->d_prow[1].p, c->d_rowptr.p,
-                                  c->d_rstart.p, c->d_colidx.p, c->d_int2ext.p, c->d_vals.p, c->d_sc.p, gcoef,
-                                  f_out, s);
+            launch::rows_dynamic(c->region(r), c->row_view(r), p, c->d_rowptr.p, c->d_rstart.p, c->d_vals.p,
+                                 c->d_sc.p, u_prev, f_out, h.pin_dof, s);
+        launch::p2_membrane(ga, c->region(0), c->region(1), c->p2_mem(), p, c->d_rowptr.p, c->d_rstart.p,
+                            c->d_vals.p, c->d_sc.p, gcoef, f_out, s);
     };
     matrix_and_rhs(false);
     if (first) {

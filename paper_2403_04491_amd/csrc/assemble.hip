@@ -1,10 +1,12 @@
-// Assembly kernels for the IMEX-linearised KNP-EMI step (eq. ``lin_sys``).
+// Assembly kernels for the IMEX-linearised KNP-EMI step (eq. ``lin_sys``): the
+// membrane coefficients, the dt-dependent static blocks, and helpers.  The per-step bulk
+// values of an order-1 mesh are in assemble_rows.hip, the membrane blocks and the
+// order-2 path in assemble_p2.hip.
 //
-// Every kernel is a deterministic gather: one thread owns one region vertex
-// (one scalar row, i.e. four global rows) and walks the elements or membrane
-// facets incident to it in a fixed order, accumulating into LDS slots indexed
-// by the row's column positions.  No floating-point atomics are used, so two
-// runs are bitwise identical.
+// The static kernel is a deterministic gather: one thread owns one region vertex (one
+// scalar row, i.e. four global rows) and walks the elements incident to it in a fixed
+// order, accumulating into LDS slots indexed by the row's column positions.  No
+// floating-point atomics are used, so two runs are bitwise identical.
 //
 // Integrals are exact for P1: on a simplex of dimension m with measure |T|,
 //   int prod lambda_a^{p_a} = m! |T| prod p_a! / (m + sum p_a)!.
@@ -199,201 +201,6 @@ __global__ void __launch_bounds__(BLK) k_static(RegionArgs ra, MeshArgs ma, Phys
         }
 }
 
-// ------------------------------------------------------------------ bulk, per-step part
-// c_r^k rows, phi_r block: tilde-tau_k A_r^k;  phi_r row, phi_r block:
-// sum_k z_k tilde-tau_k A_r^k;  RHS f_r^k = M_r c^{k,n-1}, f_r^phi = 0.
-// A_r^k uses c^{k,n-1} (exact for P1: element mean times the element stiffness).
-template <int D>
-__global__ void __launch_bounds__(BLK) k_dynamic(RegionArgs ra, MeshArgs ma, PhysArgs p,
-                                                 const int64_t *__restrict__ rowptr,
-                                                 const int64_t *__restrict__ rstart, double *__restrict__ vals,
-                                                 const double *__restrict__ sc, const double *__restrict__ u,
-                                                 double *__restrict__ f, int64_t pin_dof) {
-    __shared__ double sK[3][MAXN][BLK];
-    const int tid = threadIdx.x;
-    const int64_t j = int64_t(blockIdx.x) * BLK + tid;
-    if (j >= ra.Nr) return;
-    const int64_t p0 = ra.prow[j];
-    const int n = int(ra.prow[j + 1] - p0);
-    for (int q = 0; q < n; ++q) sK[0][q][tid] = sK[1][q][tid] = sK[2][q][tid] = 0.0;
-    const int32_t *loc = ra.r == 0 ? ma.loc_i : ma.loc_e;
-    const int64_t Nr = ra.Nr;
-    const double *cb = u + ra.off;
-    double mc[3] = {0.0, 0.0, 0.0};
-    for (int64_t t = ra.irow[j]; t < ra.irow[j + 1]; ++t) {
-        const int32_t e = ra.ielem[t];
-        const uint32_t pk = ra.ipos[t];
-        const int slot = pk & 3u;
-        int32_t vg[D + 1];
-        double x[D + 1][D], g[D + 1][D];
-        load_simplex<D>(ma, e, vg, x);
-        const double vol = simplex_grads<D>(x, g);
-        double cv[3][D + 1], cbar[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-        for (int a = 0; a <= D; ++a) {
-            const int64_t l = loc[vg[a]];
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                cv[k][a] = cb[k * Nr + l];
-                cbar[k] += cv[k][a];
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < 3; ++k) cbar[k] /= double(D + 1);
-#pragma unroll
-        for (int a = 0; a <= D; ++a) {
-            const int q = (pk >> (2 + 5 * a)) & 31u;
-            double dot = 0.0;
-#pragma unroll
-            for (int d = 0; d < D; ++d) dot += g[slot][d] * g[a][d];
-            const double K = vol * dot;
-            const double Mv = vol * mass_moment<D>(a == slot);
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                sK[k][q][tid] += cbar[k] * K;
-                mc[k] += Mv * cv[k][a];
-            }
-        }
-    }
-    const int32_t *pc = ra.pcol + p0;
-    const int64_t phib = ra.off + 3 * Nr;
-    for (int k = 0; k < 3; ++k) {
-        const int64_t row = ra.off + k * Nr + j;
-        const int64_t rp = rstart[row];
-        const int gq = int(rowptr[row + 1] - rowptr[row]) - 2 * n;
-        const int64_t seg = rp + (ra.r == 0 ? 0 : gq) + n;
-        const double sr = sc[row];
-        for (int q = 0; q < n; ++q) {
-            const int64_t col = phib + pc[q];
-            const double v = p.ttau[k] * sK[k][q][tid];
-            vals[seg + q] = col == pin_dof ? 0.0 : v * sr * sc[col];
-        }
-        f[row] = mc[k];
-    }
-    const int64_t row = phib + j;
-    const int64_t rp = rstart[row];
-    const int gq = int(rowptr[row + 1] - rowptr[row]) - 4 * n;
-    const int64_t seg = rp + (ra.r == 0 ? 0 : gq) + 3 * n;
-    const double sr = sc[row];
-    const bool pinrow = row == pin_dof;
-    for (int q = 0; q < n; ++q) {
-        const int64_t col = phib + pc[q];
-        double v = 0.0;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) v += p.z[k] * p.ttau[k] * sK[k][q][tid];
-        const bool keep = pinrow ? (col == row) : (col != pin_dof);
-        vals[seg + q] = keep ? v * sr * sc[col] : 0.0;
-    }
-    f[row] = 0.0;
-}
-
-// ------------------------------------------------------------------ membrane part
-// For a membrane vertex a in region r (sgn_r = +1 for ICS, -1 for ECS), with the
-// P1 membrane fields C_r^k, g_r^k, h_r:
-//   c_r^k row: phi_r block += int C_r^k phi_a phi_b,  phi_q block = -int C_r^k phi_a phi_b
-//   phi_r row: phi_r block += C_m/F int phi_a phi_b,  phi_q block = -C_m/F int phi_a phi_b
-//   f_r^k -= int g_r^k phi_a,  f_r^phi -= int h_r phi_a.
-constexpr int MBLK = 32;
-
-template <int D>
-__global__ void __launch_bounds__(MBLK) k_membrane(GammaArgs g, MeshArgs ma, PhysArgs p, int64_t Ni, int64_t Ne,
-                                                   const int64_t *__restrict__ prow_i,
-                                                   const int64_t *__restrict__ prow_e,
-                                                   const int64_t *__restrict__ rowptr,
-                                                   const int64_t *__restrict__ rstart, double *__restrict__ vals,
-                                                   const int32_t *__restrict__ colidx,
-                                                   const int32_t *__restrict__ int2ext,
-                                                   const double *__restrict__ sc, const double *__restrict__ gc,
-                                                   double *__restrict__ f) {
-    __shared__ double sC[3][MAXN][MBLK];
-    __shared__ double sS[MAXN][MBLK];
-    __shared__ double sX[3][MAXG][MBLK];
-    __shared__ double sXS[MAXG][MBLK];
-    const int tid = threadIdx.x;
-    const int64_t it = int64_t(blockIdx.x) * MBLK + tid;
-    if (it >= 2 * g.n_gamma) return;
-    const int r = int(it & 1);
-    const int64_t gi = it >> 1;
-    const int64_t Nr = r == 0 ? Ni : Ne, Nq = r == 0 ? Ne : Ni;
-    const int64_t offr = r == 0 ? 0 : 4 * Ni, offq = r == 0 ? 4 * Ni : 0;
-    const int64_t j = r == 0 ? g.gloc_i[gi] : g.gloc_e[gi];
-    const int64_t *prow = r == 0 ? prow_i : prow_e;
-    const int n = int(prow[j + 1] - prow[j]);
-    const uint32_t *fpos = r == 0 ? g.fpos_i : g.fpos_e;
-    const int64_t row0 = offr + j;
-    (void)Nq;
-    const int gn = int(rowptr[row0 + 1] - rowptr[row0]) - 2 * n;
-    for (int q = 0; q < n; ++q) {
-        sC[0][q][tid] = sC[1][q][tid] = sC[2][q][tid] = 0.0;
-        sS[q][tid] = 0.0;
-    }
-    for (int q = 0; q < gn; ++q) {
-        sX[0][q][tid] = sX[1][q][tid] = sX[2][q][tid] = 0.0;
-        sXS[q][tid] = 0.0;
-    }
-    double fg[4] = {0.0, 0.0, 0.0, 0.0};
-    const double cmf = p.C_m / p.F;
-    for (int64_t t = g.frow[gi]; t < g.frow[gi + 1]; ++t) {
-        const int32_t *fv = g.facets + int64_t(g.ffacet[t]) * D;
-        const uint32_t pk = fpos[t];
-        const int slot = pk & 3u;
-        const double meas = facet_measure<D>(ma, fv);
-        double Cv[3][D], gv[3][D], hv[D];
-#pragma unroll
-        for (int a = 0; a < D; ++a) {
-            const double *c = gc + int64_t(g.gidx[fv[a]]) * GC_STRIDE + r * GC_REGION;
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                Cv[k][a] = c[GC_C + k];
-                gv[k][a] = c[GC_G + k];
-            }
-            hv[a] = c[GC_H];
-        }
-#pragma unroll
-        for (int a = 0; a < D; ++a) {
-            const int qr = (pk >> (2 + 5 * a)) & 31u;
-            const int qg = (pk >> (17 + 4 * a)) & 15u;
-            const double m2 = meas * fmom2<D>(slot, a);
-            sS[qr][tid] += cmf * m2;
-            sXS[qg][tid] -= cmf * m2;
-            fg[3] -= hv[a] * m2;
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                fg[k] -= gv[k][a] * m2;
-                double w = 0.0;
-#pragma unroll
-                for (int c = 0; c < D; ++c) w += Cv[k][c] * fmom3<D>(slot, a, c);
-                w *= meas;
-                sC[k][qr][tid] += w;
-                sX[k][qg][tid] -= w;
-            }
-        }
-    }
-    // write: phi_r block adds to the bulk values of this row (this thread owns it);
-    // phi_q block (membrane neighbours, ascending) is written outright
-    for (int k = 0; k < 4; ++k) {
-        const int64_t row = offr + k * Nr + j;
-        const int64_t rp = rstart[row];
-        const int nb = k < 3 ? 1 : 3;              // blocks preceding phi_r in this row
-        const int64_t seg_phi = rp + (r == 0 ? 0 : gn) + int64_t(nb) * n;
-        const int64_t seg_q = r == 0 ? rp + int64_t(nb + 1) * n : rp;
-        const double sr = sc[row];
-        for (int q = 0; q < n; ++q) {
-            const int64_t pos = seg_phi + q;
-            const double add = k < 3 ? sC[k][q][tid] : sS[q][tid];
-            vals[pos] += add * sr * sc[int2ext[colidx[pos]]];
-        }
-        for (int q = 0; q < gn; ++q) {
-            const int64_t pos = seg_q + q;
-            const double v = k < 3 ? sX[k][q][tid] : sXS[q][tid];
-            vals[pos] = v * sr * sc[int2ext[colidx[pos]]];
-        }
-        f[row] += fg[k];
-    }
-    (void)Nq;
-    (void)offq;
-}
-
 // ------------------------------------------------------------------ helpers
 __global__ void k_check_finite(const double *__restrict__ u, int64_t n, int *flag) {
     for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
@@ -485,32 +292,6 @@ void assemble_static(const RegionArgs &ra, const MeshArgs &ma, const PhysArgs &p
     else
         hipLaunchKernelGGL(k_static<3>, dim3(nblocks(ra.Nr, BLK)), dim3(BLK), 0, s, ra, ma, p, rowptr, rstart, vals,
                            sc, pin_dof);
-}
-
-void assemble_dynamic(const RegionArgs &ra, const MeshArgs &ma, const PhysArgs &p, const int64_t *rowptr,
-                      const int64_t *rstart, double *vals, const double *sc, const double *u_prev, double *f,
-                      int64_t pin_dof, hipStream_t s) {
-    if (ra.Nr == 0) return;
-    if (ma.dim == 2)
-        hipLaunchKernelGGL(k_dynamic<2>, dim3(nblocks(ra.Nr, BLK)), dim3(BLK), 0, s, ra, ma, p, rowptr, rstart, vals,
-                           sc, u_prev, f, pin_dof);
-    else
-        hipLaunchKernelGGL(k_dynamic<3>, dim3(nblocks(ra.Nr, BLK)), dim3(BLK), 0, s, ra, ma, p, rowptr, rstart, vals,
-                           sc, u_prev, f, pin_dof);
-}
-
-void assemble_membrane(const GammaArgs &g, const MeshArgs &ma, const PhysArgs &p, int64_t Ni, int64_t Ne,
-                       const int64_t *prow_i, const int64_t *prow_e, const int64_t *rowptr, const int64_t *rstart,
-                       const int32_t *colidx, const int32_t *int2ext, double *vals, const double *sc,
-                       const double *gcoef, double *f, hipStream_t s) {
-    if (g.n_gamma == 0) return;
-    const unsigned nb = nblocks(2 * g.n_gamma, MBLK);
-    if (ma.dim == 2)
-        hipLaunchKernelGGL(k_membrane<2>, dim3(nb), dim3(MBLK), 0, s, g, ma, p, Ni, Ne, prow_i, prow_e, rowptr,
-                           rstart, vals, colidx, int2ext, sc, gcoef, f);
-    else
-        hipLaunchKernelGGL(k_membrane<3>, dim3(nb), dim3(MBLK), 0, s, g, ma, p, Ni, Ne, prow_i, prow_e, rowptr,
-                           rstart, vals, colidx, int2ext, sc, gcoef, f);
 }
 
 void scaling_from_diag(int64_t N, const double *vals, const int64_t *diag_pos, double *sc, hipStream_t s) {

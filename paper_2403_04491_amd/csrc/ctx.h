@@ -61,6 +61,12 @@ struct knp_ctx {
     knp::DArray<int32_t> d_p2_wnode[2], d_p2_erow[2], d_p2_rpos[2], d_p2_mrow, d_p2_cnode, d_gcol;
     knp::DArray<double> d_p2_wval[2], d_p2_sval[2], d_p2_mval[2], d_p2_mg, d_p2_cval;
     int64_t p2_nent[2] = {0, 0}, p2_nmem = 0;
+    // order 1 within the walk limits: the row terms of the per-step bulk values
+    bool rows = false;
+    int64_t rows_ngroups[2] = {0, 0};
+    knp::DArray<knp::RowGroup> d_rgroups[2];
+    knp::DArray<uint8_t> d_rcount[2], d_rslot[2];
+    knp::DArray<double> d_rval[2], d_rmval[2];
     knp::DArray<int64_t> d_cgrow;   // membrane vertices of each cell (CSR)
     knp::DArray<int32_t> d_cgcol;
     knp::DArray<double> d_thv;      // per membrane vertex theta adjoint (VJP scratch)
@@ -129,6 +135,16 @@ struct knp_ctx {
         b.sval = d_p2_sval[r].p;
         b.mval = d_p2_mval[r].p;
         return b;
+    }
+    knp::launch::RowView row_view(int r) const {
+        knp::launch::RowView v;
+        v.ngroups = rows_ngroups[r];
+        v.groups = d_rgroups[r].p;
+        v.tcount = d_rcount[r].p;
+        v.tslot = d_rslot[r].p;
+        v.tval = d_rval[r].p;
+        v.mval = d_rmval[r].p;
+        return v;
     }
     knp::launch::P2Mem p2_mem() const {
         knp::launch::P2Mem m;

@@ -118,6 +118,42 @@ struct P2Host {
     std::vector<double> cval;
 };
 void build_p2_operators(const HostMesh &m, P2Host &out);   // throws Error
+// the two halves of it: the bulk operators (sval, mval, erow, the w terms) and the
+// membrane ones (mrow, mg, the c terms, rpos)
+void build_p2_bulk(const HostMesh &m, P2Host &out);
+void build_p2_membrane(const HostMesh &m, P2Host &out);
+
+// ----------------------------------------------------------------------------- row terms
+// The per-step bulk values of an order-1 mesh as sparse products with the nodal
+// concentrations, laid out for one wavefront per group of consecutive rows.  For the
+// row vertex i and an off-diagonal column j of region r,
+//   int c_h grad phi_i . grad phi_j = sum_{T containing i, j} |T| G_ij(T) cbar_T,
+// with G_ij = grad lambda_i . grad lambda_j and cbar_T the mean of c over the d + 1
+// vertices of T (exact for P1).  Each element around the edge (i, j) holds d - 1 further
+// vertices p (the edge's ring), so with w_p = sum_{T containing i, j, p} |T| G_ij(T)/(d+1)
+//   int c_h grad phi_i . grad phi_j = sum_p w_p c_p + (sum_p w_p) (c_i + c_j)/(d - 1),
+// and since sum_j G_ij(T) = 0 the diagonal value is minus the sum of the row's
+// off-diagonal ones.  Every ring vertex is a neighbour of i, so a term is stored as
+// (position of p in row i, w_p).  Weights below 32 eps of the row's largest are the
+// rounding residue of integrals that vanish (right-angled elements) and are dropped.
+struct RowGroup {
+    int64_t term0;      // first term of the group
+    uint64_t starts;    // bit x: the group's entry x is the first of a row
+    int32_t row0;       // first row (region-local vertex)
+    int16_t tmax;       // most terms of one entry in the group
+    int16_t nmax;       // longest row of the group
+};
+struct RowTerms {
+    std::vector<RowGroup> groups;   // [ngroups + 1]; the last holds row0 = N_r, term0 = all terms
+    std::vector<uint8_t> tcount;    // [entries] terms of each entry of the region's pattern
+    std::vector<uint8_t> tslot;     // [terms] position of the weight's vertex in the row
+    std::vector<double> tval;       // [terms]
+    std::vector<double> mval;       // [entries] int phi_i phi_j
+};
+constexpr int ROW_GROUP = 64;       // entries per group: one wavefront
+// Builds both regions' row terms of an order-1 mesh; false (nothing built) if a row has
+// more than ROW_GROUP entries.
+bool build_row_terms(const HostMesh &m, RowTerms out[2]);
 
 // ----------------------------------------------------------------------------- device buffer
 template <typename T>
@@ -377,6 +413,16 @@ struct P2Mem {
     const int32_t *gcol = nullptr, *mrow = nullptr, *cnode = nullptr, *rpos_i = nullptr, *rpos_e = nullptr;
     const double *mg = nullptr, *cval = nullptr;
 };
+// order-1 per-step bulk values from the row terms (RowTerms on the device)
+struct RowView {
+    int64_t ngroups = 0;
+    const RowGroup *groups = nullptr;   // [ngroups + 1]
+    const uint8_t *tcount = nullptr, *tslot = nullptr;
+    const double *tval = nullptr, *mval = nullptr;
+};
+void rows_dynamic(const RegionArgs &ra, const RowView &rv, const PhysArgs &p, const int64_t *rowptr,
+                  const int64_t *rstart, double *vals, const double *sc, const double *u_prev, double *f,
+                  int64_t pin_dof, hipStream_t s);
 // the dt-dependent static blocks of one region (c rows: M + tau_k A; phi row: z_k tau_k A)
 void p2_static(const RegionArgs &ra, const P2Bulk &b, const PhysArgs &p, const int64_t *rowptr, const int64_t *rstart,
                double *vals, const double *sc, int64_t pin_dof, hipStream_t s);
@@ -401,13 +447,6 @@ void membrane_coefficients(const GammaArgs &g, const PhysArgs &p, int64_t Ni, in
 void assemble_static(const RegionArgs &ra, const MeshArgs &ma, const PhysArgs &p,
                      const int64_t *rowptr, const int64_t *rstart, double *vals, const double *sc, int64_t pin_dof,
                      hipStream_t s);
-void assemble_dynamic(const RegionArgs &ra, const MeshArgs &ma, const PhysArgs &p,
-                      const int64_t *rowptr, const int64_t *rstart, double *vals, const double *sc,
-                      const double *u_prev, double *f, int64_t pin_dof, hipStream_t s);
-void assemble_membrane(const GammaArgs &g, const MeshArgs &ma, const PhysArgs &p, int64_t Ni, int64_t Ne,
-                       const int64_t *prow_i, const int64_t *prow_e, const int64_t *rowptr, const int64_t *rstart,
-                       const int32_t *colidx, const int32_t *int2ext, double *vals, const double *sc,
-                       const double *gcoef, double *f, hipStream_t s);
 // solver order (off_r + 4 j + f) <-> ABI order (off_r + f N_r + j); int2ext maps the
 // first to the second; mode 0: times sc, 1: divided by sc, 2: plain copy
 void to_internal(int64_t n, const int32_t *int2ext, const double *x, const double *sc, double *y, int mode,

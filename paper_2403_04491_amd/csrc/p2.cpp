@@ -53,6 +53,11 @@ struct Terms {
 }  // namespace
 
 void build_p2_operators(const HostMesh &m, P2Host &out) {
+    build_p2_bulk(m, out);
+    build_p2_membrane(m, out);
+}
+
+void build_p2_bulk(const HostMesh &m, P2Host &out) {
     const int d = m.dim, n = d + 1, nv = m.nv_elem, nf = m.nv_facet;
     const p2::RefTensors T = p2::reference_tensors(d, m.order);
     if (T.nb != nv || T.nf != nf) fail_internal("element node counts");
@@ -129,7 +134,12 @@ void build_p2_operators(const HostMesh &m, P2Host &out) {
                 std::copy(rows[j][q].val.begin(), rows[j][q].val.end(), out.wval[r].begin() + o);
             }
     }
-    // membrane
+}
+
+void build_p2_membrane(const HostMesh &m, P2Host &out) {
+    const int d = m.dim, nf = m.nv_facet;
+    const p2::RefTensors T = p2::reference_tensors(d, m.order);
+    if (T.nf != nf) fail_internal("facet node counts");
     const int64_t ng = int64_t(m.gamma.size()), nmem = m.grow[ng];
     out.mg.assign(std::max<int64_t>(1, nmem), 0.0);
     out.mrow.assign(std::max<int64_t>(1, nmem), 0);
