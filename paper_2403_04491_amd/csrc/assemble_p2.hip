@@ -104,10 +104,12 @@ __global__ void k_p2_membrane(GammaArgs g, RegionArgs ra_i, RegionArgs ra_e, P2M
                               const int64_t *__restrict__ rowptr, const int64_t *__restrict__ rstart,
                               double *__restrict__ vals, const double *__restrict__ sc,
                               const double *__restrict__ gc, double *__restrict__ f) {
+    // threads [0, nmem) serve region i, [nmem, 2 nmem) region e: consecutive threads take
+    // consecutive entries of one region, so a membrane row's values are written together
     const int64_t it = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (it >= 2 * mm.nmem) return;
-    const int r = int(it & 1);
-    const int64_t e = it >> 1;
+    const int r = it < mm.nmem ? 0 : 1;
+    const int64_t e = it - r * mm.nmem;
     const int64_t gi = mm.mrow[e];
     const int64_t e0 = mm.grow[gi];
     const int gn = int(mm.grow[gi + 1] - e0);
