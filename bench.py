@@ -167,15 +167,15 @@ def source_digests():
     return out
 
 
-def measured_traffic(kernel, precision):
+def measured_traffic(kernel, precision, n):
     """Calibrated HBM bytes per launch of `kernel`, or None if not measured on the
-    current sources."""
+    current sources or on a workload of another size (n unknowns)."""
     try:
         with open(TRAFFIC_FILE) as fh:
             rec = json.load(fh)
     except (OSError, ValueError):
         return None
-    if rec.get("sources_sha256") != source_digests():
+    if rec.get("sources_sha256") != source_digests() or rec.get("N") != n:
         return None
     k = rec.get("kernels", {}).get(precision, {}).get(kernel)
     return None if k is None else k.get("bytes_per_launch")
@@ -204,7 +204,7 @@ def roofline_of(timers, precision=None, info=None):
     per_launch_bytes = t["bytes"] / t["launches"]
     avg_s = t["total_ms"] / t["launches"] * 1e-3
     achieved = per_launch_bytes / avg_s / 1e9
-    traffic = measured_traffic(best, precision) if precision else None
+    traffic = measured_traffic(best, precision, info.N) if (precision and info is not None) else None
     out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
            "kernel": best, "bytes_per_launch": per_launch_bytes,
@@ -365,8 +365,7 @@ def model_a_bench(args, log):
         spikes.append({"stimulus_ms": round(on * case.dt * 1e3, 3),
                        "crosses_0mV_ms": None if len(up) == 0 else round((on + 1 + up[0]) * case.dt * 1e3, 3),
                        "peak_mV": round(float(seg.max()) * 1e3, 2)})
-    kernel, roof = roofline_of(timers, "fp32_amg")
-    roof["traffic"] = None          # the counters were taken on the 132^3 lattice, not here
+    kernel, roof = roofline_of(timers, "fp32_amg")   # no traffic: the counters are the lattice's
     sample_steps = [0, 1, 2, 5, 10, 20, 50, 100, 101, 105, 150, 200, 205, 250, n_steps]
     traces = {}
     for membrane in (("hh", "kir", "leak") if args.ma_trace_nx > 0 else ()):
