@@ -25,6 +25,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <memory>
 #include <numeric>
 #include <type_traits>
 
@@ -35,24 +36,67 @@ namespace knp {
 
 namespace {
 
+// A^T with each row's entries in ascending column order (the order a serial
+// transpose writes them): the threads take contiguous row ranges of A, count their
+// entries per column, and each writes its range after the earlier threads' entries.
 Csr transpose(const Csr &A) {
     Csr T;
     T.nrows = A.ncols;
     T.ncols = A.nrows;
     T.rowptr.assign(T.nrows + 1, 0);
     const int64_t nnz = A.nnz();
-    for (int64_t k = 0; k < nnz; ++k) T.rowptr[A.col[k] + 1]++;
-    for (int64_t i = 0; i < T.nrows; ++i) T.rowptr[i + 1] += T.rowptr[i];
+    const int nt = std::max(1, std::min<int>(omp_get_max_threads(), int(A.nrows / 4096) + 1));
+    std::vector<std::vector<int64_t>> cnt(nt);
+    std::vector<int64_t> r0(nt + 1);
+    for (int t = 0; t <= nt; ++t) r0[t] = A.nrows * t / nt;
+#pragma omp parallel for num_threads(nt) schedule(static, 1)
+    for (int t = 0; t < nt; ++t) {
+        cnt[t].assign(T.nrows, 0);
+        for (int64_t k = A.rowptr[r0[t]]; k < A.rowptr[r0[t + 1]]; ++k) cnt[t][A.col[k]]++;
+    }
+    // per column: the start of each thread's entries, and the row pointers
+    int64_t run = 0;
+    for (int64_t c = 0; c < T.nrows; ++c) {
+        T.rowptr[c] = run;
+        for (int t = 0; t < nt; ++t) {
+            const int64_t k = cnt[t][c];
+            cnt[t][c] = run;
+            run += k;
+        }
+    }
+    T.rowptr[T.nrows] = run;
     T.col.resize(nnz);
     T.val.resize(nnz);
-    std::vector<int64_t> fill(T.rowptr.begin(), T.rowptr.end() - 1);
-    for (int64_t i = 0; i < A.nrows; ++i)
-        for (int64_t k = A.rowptr[i]; k < A.rowptr[i + 1]; ++k) {
-            const int64_t p = fill[A.col[k]]++;
-            T.col[p] = int32_t(i);
-            T.val[p] = A.val[k];
-        }
+#pragma omp parallel for num_threads(nt) schedule(static, 1)
+    for (int t = 0; t < nt; ++t) {
+        std::vector<int64_t> &fill = cnt[t];
+        for (int64_t i = r0[t]; i < r0[t + 1]; ++i)
+            for (int64_t k = A.rowptr[i]; k < A.rowptr[i + 1]; ++k) {
+                const int64_t p = fill[A.col[k]]++;
+                T.col[p] = int32_t(i);
+                T.val[p] = A.val[k];
+            }
+    }
     return T;
+}
+
+// sum over i < n of f(i) in fixed chunks, the chunk sums added in order: the result does
+// not depend on the number of threads
+template <class F>
+double det_sum(int64_t n, F f) {
+    constexpr int64_t CH = int64_t(1) << 14;
+    const int64_t nch = (n + CH - 1) / CH;
+    std::vector<double> part(nch);
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < nch; ++c) {
+        double acc = 0.0;
+        const int64_t e = std::min(n, (c + 1) * CH);
+        for (int64_t i = c * CH; i < e; ++i) acc += f(i);
+        part[c] = acc;
+    }
+    double tot = 0.0;
+    for (double v : part) tot += v;
+    return tot;
 }
 
 // Drops the couplings of a coarse operator with |a_ij| < tol sqrt(a_ii a_jj) and
@@ -86,7 +130,7 @@ void sparsify(Csr &A, const std::vector<double> &b, double tol) {
     Csr K;
     K.nrows = A.nrows;
     K.ncols = A.ncols;
-    K.rowptr = cnt;
+    K.rowptr.assign(cnt.begin(), cnt.end());
     K.col.resize(cnt[n]);
     K.val.resize(cnt[n]);
 #pragma omp parallel for schedule(static)
@@ -178,16 +222,16 @@ double gershgorin(const Csr &A) {
     return m;
 }
 
-// power iteration on a symmetric unit-diagonal operator (deterministic start)
+// power iteration on a symmetric unit-diagonal operator (deterministic start and sums)
 double power_lmax(const Csr &A, int iters) {
     const int64_t n = A.nrows;
     std::vector<double> x(n), y(n);
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) x[i] = 1.0 + 0.5 * std::sin(0.7 * double(i) + 0.3);
     double lam = 0.0;
     for (int it = 0; it < iters; ++it) {
-        double nx = 0.0;
-        for (int64_t i = 0; i < n; ++i) nx += x[i] * x[i];
-        nx = std::sqrt(nx);
+        const double nx = std::sqrt(det_sum(n, [&](int64_t i) { return x[i] * x[i]; }));
+#pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < n; ++i) x[i] /= nx;
 #pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < n; ++i) {
@@ -195,9 +239,7 @@ double power_lmax(const Csr &A, int iters) {
             for (int64_t k = A.rowptr[i]; k < A.rowptr[i + 1]; ++k) s += A.val[k] * x[A.col[k]];
             y[i] = s;
         }
-        double xy = 0.0;
-        for (int64_t i = 0; i < n; ++i) xy += x[i] * y[i];
-        lam = xy;
+        lam = det_sum(n, [&](int64_t i) { return x[i] * y[i]; });
         std::swap(x, y);
     }
     return lam;
@@ -296,27 +338,33 @@ void DevCsr::upload(const Csr &h, bool fp32, hipStream_t s) {
     ncols = h.ncols;
     nnz = h.nnz();
     rowptr.alloc(h.rowptr.size());
-    rowptr.upload(h.rowptr, s);
+    rowptr.upload(h.rowptr.data(), h.rowptr.size(), s);
     {
         std::vector<int32_t> b = row_blocks(h.rowptr.data(), h.nrows);
         nblk = int64_t(b.size()) - 1;
         blk.alloc(b.size());
         blk.upload(b, s);
     }
-    std::vector<int32_t> c(h.col);
-    c.resize(h.col.size() + STREAM_PAD, 0);
-    col.alloc(c.size());
-    col.upload(c, s);
+    // columns and values, then STREAM_PAD zeros after each
+    const size_t nz = h.col.size();
+    const int32_t zc[STREAM_PAD] = {};
+    col.alloc(nz + STREAM_PAD);
+    if (nz) hip_check(hipMemcpyAsync(col.p, h.col.data(), nz * sizeof(int32_t), hipMemcpyHostToDevice, s), "col");
+    hip_check(hipMemcpyAsync(col.p + nz, zc, sizeof(zc), hipMemcpyHostToDevice, s), "col pad");
     if (fp32) {
-        std::vector<float> v(h.val.begin(), h.val.end());
-        v.resize(h.val.size() + STREAM_PAD, 0.0f);
-        val32.alloc(v.size());
-        val32.upload(v, s);
+        std::unique_ptr<float[]> v(new float[nz + STREAM_PAD]);
+#pragma omp parallel for schedule(static)
+        for (int64_t k = 0; k < int64_t(nz); ++k) v[k] = float(h.val[k]);
+        for (int k = 0; k < STREAM_PAD; ++k) v[nz + k] = 0.0f;
+        val32.alloc(nz + STREAM_PAD);
+        val32.upload(v.get(), nz + STREAM_PAD, s);
+        hip_check(hipStreamSynchronize(s), "upload");
     } else {
-        std::vector<double> v(h.val);
-        v.resize(h.val.size() + STREAM_PAD, 0.0);
-        val64.alloc(v.size());
-        val64.upload(v, s);
+        const double zv[STREAM_PAD] = {};
+        val64.alloc(nz + STREAM_PAD);
+        if (nz) hip_check(hipMemcpyAsync(val64.p, h.val.data(), nz * sizeof(double), hipMemcpyHostToDevice, s), "val");
+        hip_check(hipMemcpyAsync(val64.p + nz, zv, sizeof(zv), hipMemcpyHostToDevice, s), "val pad");
+        hip_check(hipStreamSynchronize(s), "upload");
     }
     hip_check(hipStreamSynchronize(s), "upload");
 }
@@ -347,8 +395,10 @@ void upload_field_blocks(DevFieldBlock &fb, const HostMesh &m, const std::vector
     for (int64_t j = 0; j <= fb.Ni; ++j) rp[j] = m.prow[0][j];
     for (int64_t j = 1; j <= fb.Ne; ++j) rp[fb.Ni + j] = nnz0 + m.prow[1][j];
     std::vector<int32_t> col(std::max<int64_t>(1, fb.nnz));
-    std::copy(m.pcol[0].begin(), m.pcol[0].begin() + nnz0, col.begin());
-    std::copy(m.pcol[1].begin(), m.pcol[1].begin() + nnz1, col.begin() + nnz0);
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < nnz0; ++k) col[k] = m.pcol[0][k];
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < nnz1; ++k) col[nnz0 + k] = m.pcol[1][k];
     // row blocks per region, region e's rows after region i's
     std::vector<int32_t> blk = row_blocks(m.prow[0].data(), fb.Ni, FB_CAP);
     {
@@ -356,12 +406,17 @@ void upload_field_blocks(DevFieldBlock &fb, const HostMesh &m, const std::vector
         for (size_t q = 1; q < be.size(); ++q) blk.push_back(int32_t(fb.Ni + be[q]));
     }
     fb.nblk = int64_t(blk.size()) - 1;
-    std::vector<double> v(std::max<int64_t>(4, 4 * fb.nnz));
+    // the four field values of each entry side by side, in the level's precision
+    const size_t nv = size_t(std::max<int64_t>(4, 4 * fb.nnz));
     const int64_t pbase[2] = {0, 4 * nnz0}, nnzr[2] = {nnz0, nnz1}, kbase[2] = {0, nnz0};
-    for (int r = 0; r < 2; ++r)
+    auto fill = [&](auto *v) {
+        for (int r = 0; r < 2; ++r)
 #pragma omp parallel for schedule(static)
-        for (int64_t k = 0; k < nnzr[r]; ++k)
-            for (int f = 0; f < 4; ++f) v[4 * (kbase[r] + k) + f] = p0_vals[pbase[r] + f * nnzr[r] + k];
+            for (int64_t k = 0; k < nnzr[r]; ++k)
+                for (int f = 0; f < 4; ++f)
+                    v[4 * (kbase[r] + k) + f] = decltype(+v[0])(p0_vals[pbase[r] + f * nnzr[r] + k]);
+        for (size_t k = size_t(4 * fb.nnz); k < nv; ++k) v[k] = 0;
+    };
     fb.rowptr.alloc(rp.size());
     fb.rowptr.upload(rp, s);
     fb.col.alloc(col.size());
@@ -369,14 +424,18 @@ void upload_field_blocks(DevFieldBlock &fb, const HostMesh &m, const std::vector
     fb.blk.alloc(blk.size());
     fb.blk.upload(blk, s);
     if (fp32) {
-        std::vector<float> v32(v.begin(), v.end());
-        fb.val32.alloc(v32.size());
-        fb.val32.upload(v32, s);
+        std::unique_ptr<float[]> v(new float[nv]);
+        fill(v.get());
+        fb.val32.alloc(nv);
+        fb.val32.upload(v.get(), nv, s);
+        hip_check(hipStreamSynchronize(s), "field-block upload");
     } else {
-        fb.val64.alloc(v.size());
-        fb.val64.upload(v, s);
+        std::unique_ptr<double[]> v(new double[nv]);
+        fill(v.get());
+        fb.val64.alloc(nv);
+        fb.val64.upload(v.get(), nv, s);
+        hip_check(hipStreamSynchronize(s), "field-block upload");
     }
-    hip_check(hipStreamSynchronize(s), "field-block upload");
 }
 
 }  // namespace
@@ -503,11 +562,14 @@ void amg_build(Amg &amg, const HostMesh &m, const std::vector<double> &p0_vals, 
         for (int64_t i = 0; i < n; ++i) AF.rowptr[i + 1] = AF.rowptr[i] + 1 + (srow[i + 1] - srow[i]);
         AF.col.resize(AF.rowptr[n]);
         AF.val.resize(AF.rowptr[n]);
-#pragma omp parallel for schedule(static)
+#pragma omp parallel
+        {
+        std::vector<std::pair<int32_t, double>> e;
+#pragma omp for schedule(static)
         for (int64_t i = 0; i < n; ++i) {
             double diag = 0.0, lump = 0.0;
             int64_t ks = srow[i];
-            std::vector<std::pair<int32_t, double>> e;
+            e.clear();
             for (int64_t k = L.A.rowptr[i]; k < L.A.rowptr[i + 1]; ++k) {
                 const int32_t j = L.A.col[k];
                 if (j == i) {
@@ -529,6 +591,7 @@ void amg_build(Amg &amg, const HostMesh &m, const std::vector<double> &p0_vals, 
                 AF.val[oo] = pr.second;
                 ++oo;
             }
+        }
         }
         // omega / rho(D_F^{-1} A_F) with a Gershgorin bound
         double rho = 0.0;

@@ -6,6 +6,8 @@
 #include <hip/hip_runtime_api.h>
 
 #include <cstdint>
+#include <memory>
+#include <utility>
 #include <string>
 #include <vector>
 
@@ -197,11 +199,35 @@ struct Timers {
 };
 
 // ----------------------------------------------------------------------------- AMG
+// Host arrays of the AMG setup: resize() leaves new elements uninitialised (every
+// producer writes all of them), so the multi-GB level arrays are not first zeroed by
+// one thread; assign() and value-constructing calls still initialise.
+template <class T>
+struct NoInitAlloc : std::allocator<T> {
+    template <class U>
+    struct rebind {
+        using other = NoInitAlloc<U>;
+    };
+    NoInitAlloc() = default;
+    template <class U>
+    NoInitAlloc(const NoInitAlloc<U> &) noexcept {}
+    template <class U>
+    void construct(U *p) noexcept {
+        ::new (static_cast<void *>(p)) U;
+    }
+    template <class U, class... Args>
+    void construct(U *p, Args &&...args) {
+        ::new (static_cast<void *>(p)) U(std::forward<Args>(args)...);
+    }
+};
+template <class T>
+using hvec = std::vector<T, NoInitAlloc<T>>;
+
 struct Csr {
     int64_t nrows = 0, ncols = 0;
-    std::vector<int64_t> rowptr;
-    std::vector<int32_t> col;
-    std::vector<double> val;
+    hvec<int64_t> rowptr;
+    hvec<int32_t> col;
+    hvec<double> val;
     int64_t nnz() const { return rowptr.empty() ? 0 : rowptr.back(); }
 };
 
