@@ -27,7 +27,7 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0
 # tolerances tried on the last step's system for the FP32-level solve that meets 1e-6 in
 # every block against the FP64 reference
-ACCURACY_RTOLS = (1e-8, 1e-9, 1e-10, 1e-11)
+ACCURACY_RTOLS = (1e-7, 1e-8, 1e-9, 1e-10, 1e-11)
 
 
 def block_errors(info, u, ref):
@@ -322,7 +322,7 @@ def model_a_bench(args, log):
 
     def run(nx, membrane, n_steps, timed):
         case = model_a_evolution_case(nx=nx, membrane=membrane, n_steps=n_steps)
-        s = KnpSolver(case, amg=amg_opts(precision=1, **ma_amg),
+        s = KnpSolver(case, gauge=args.gauge, amg=amg_opts(precision=1, **ma_amg),
                       solve=solve_opts(rtol=1e-6, restart=30, max_it=2000), order=order)
         ri, re = s.membrane_rows()
         trace = torch.empty((n_steps + 1, ri.numel()), dtype=torch.float64, device=s.dev)
@@ -383,7 +383,7 @@ def model_a_bench(args, log):
         # the time-dependent P_n: the hierarchy rebuilt from every step's matrix
         m = min(args.ma_pn_steps, n_steps)
         case_n = model_a_evolution_case(nx=nx, membrane="hh", n_steps=m)
-        sn = KnpSolver(case_n, amg=amg_opts(precision=1, operator_step=1, **ma_amg),
+        sn = KnpSolver(case_n, gauge=args.gauge, amg=amg_opts(precision=1, operator_step=1, **ma_amg),
                        solve=solve_opts(rtol=1e-6, restart=30, max_it=2000), order=order)
         its_n, t_n = [], []
         for n in range(1, m + 1):
@@ -432,7 +432,8 @@ def model_a_bench(args, log):
         "config": {"workload": f"Model A, 2D unit square with one cell, N_x={nx}, p={order}, N={s.info.N} unknowns, HH with "
                                f"the periodic Na stimulus on Gamma, uniform initial data, dt=0.1 ms, {n_steps} steps, "
                                f"FGMRES(30) + AMG(P_0) FP32 levels, rtol 1e-6",
-                   "N": s.info.N, "nnz_A": s.info.nnz_A, "parallelism": "1 GPU", "amg": ma_amg},
+                   "N": s.info.N, "nnz_A": s.info.nnz_A, "parallelism": "1 GPU", "gauge": args.gauge,
+                   "amg": ma_amg},
         "first_step_s": round(t_first, 3),
         "ms_per_step_max": round(1e3 * times.max(), 3),
         "its_per_step": {"min": int(its[1:].min()), "max": int(its[1:].max()), "mean": round(float(its[1:].mean()), 3),
@@ -475,7 +476,7 @@ def config2_bench(args, log):
     for prec in (0, 1):
         name = "fp64" if prec == 0 else "fp32_amg"
         case = config_case(2)
-        s = KnpSolver(case, amg=amg_opts(precision=prec, **amg_flags(args)),
+        s = KnpSolver(case, gauge=args.gauge, amg=amg_opts(precision=prec, **amg_flags(args)),
                       solve=solve_opts(rtol=1e-6, restart=30, max_it=4000))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -519,7 +520,8 @@ def config2_bench(args, log):
         "ms_per_step": runs["fp64"]["ms_per_step"], "higher_is_better": True, "dtype": "f64",
         "data": "synthetic", "vs_baseline": None,
         "config": {"workload": "3D Model A: [0,1]^3 um, one cell [0.25,0.75]^3, 32^3 x 6 tets, N=149,900, "
-                               "Hodgkin-Huxley with the stimulus, dt=0.05 ms, 100 steps, FGMRES(30) rtol 1e-6"},
+                               "Hodgkin-Huxley with the stimulus, dt=0.05 ms, 100 steps, FGMRES(30) rtol 1e-6",
+                   "gauge": args.gauge},
         "by_precision": runs,
     }
     print(json.dumps(out), flush=True)
@@ -647,7 +649,8 @@ def large_bench(args, log):
     log(f"case {case.name}: {case.n_vert} vertices, {case.n_elem} tets, generated in {time.perf_counter() - t0:.1f} s")
     sample("start")
     t0 = time.perf_counter()
-    solver = KnpSolver(case, amg=amg_opts(precision=1), solve=solve_opts(rtol=1e-6, restart=30, max_it=2000))
+    solver = KnpSolver(case, gauge=args.gauge, amg=amg_opts(precision=1),
+                       solve=solve_opts(rtol=1e-6, restart=30, max_it=2000))
     torch.cuda.synchronize()
     t_upload = time.perf_counter() - t0
     info = solver.info
@@ -713,7 +716,7 @@ def large_bench(args, log):
         "config": {"workload": f"8x8x8 lattice of 4:1:1 jittered box cells, {case.shape[0]}x{case.shape[1]}x"
                                f"{case.shape[2]} grid x 6 tets, N={info.N} unknowns, passive leak, dt=0.05 ms, "
                                f"FGMRES(30) rtol 1e-6",
-                   "N": info.N, "nnz_A": info.nnz_A, "nnz_P0": info.nnz_P0},
+                   "N": info.N, "nnz_A": info.nnz_A, "nnz_P0": info.nnz_P0, "gauge": args.gauge},
         "its_per_step": its, "step_ms": [round(t * 1e3, 1) for t in times],
         "first_step": {"restart": args.large_first_restart, "its": inf1.its, "rel_res": inf1.rel_res,
                        "converged": ok1, "s": round(t_first, 2),
@@ -746,6 +749,9 @@ def main():
     ap.add_argument("--first-restart", type=int, default=200,
                     help="FGMRES restart of the untimed first step (later steps: 30)")
     ap.add_argument("--restart", type=int, default=30)
+    ap.add_argument("--gauge", type=int, default=1, choices=[0, 1],
+                    help="0: point condition on phi_e in the system; 1: system without it, the "
+                         "constant-potential nullspace handled by the solve (knp_set_gauge)")
     ap.add_argument("--cheb-degree", type=int, default=5)
     ap.add_argument("--cheb-ratio", type=float, default=2.5)
     ap.add_argument("--strength", type=float, default=0.6)
@@ -831,7 +837,7 @@ def main():
     log(f"case {case.name}: {case.n_vert} vertices, {case.n_elem} tets, generated in {t_gen:.1f} s")
     t0 = time.perf_counter()
     amg_kw = amg_flags(args)
-    solver = KnpSolver(case, solve=solve_opts(rtol=1e-6, restart=args.restart, max_it=2000))
+    solver = KnpSolver(case, solve=solve_opts(rtol=1e-6, restart=args.restart, max_it=2000), gauge=args.gauge)
     torch.cuda.synchronize()
     t_upload = time.perf_counter() - t0
     info = solver.info
@@ -904,7 +910,7 @@ def main():
         "config": {"workload": f"4x4x4 lattice of jittered box cells, {case.shape[0]}^3 grid x 6 tets, "
                                f"N={info.N} unknowns, 16 HH + 48 {'leak' if args.passive == 'leak' else 'Kir-Na/K'} cells, dt=0.05 ms, FGMRES({args.restart}) rtol 1e-6",
                    "N": info.N, "nnz_A": info.nnz_A, "nnz_P0": info.nnz_P0, "parallelism": "1 GPU",
-                   "amg": amg_kw},
+                   "gauge": args.gauge, "amg": amg_kw},
         "its_per_step": {k: float(sum(r["its"]) / len(r["its"])) for k, r in runs.items()},
         "steps_per_s": {k: round(r["steps_per_s"], 3) for k, r in runs.items()},
         "ms_per_step_by_precision": {k: round(r["ms_per_step"], 2) for k, r in runs.items()},

@@ -229,6 +229,26 @@ knp_status knp_assemble_step(knp_ctx *ctx, double t_n, double dt, const double *
 knp_status knp_assemble_step_noalloc(knp_ctx *ctx, double t_n, double dt, const double *u_prev,
                                      double *gates, const double *theta, double *f_out);
 
+/* How the constant-potential nullspace of the system (Remark ``rem:nullspace``) is
+ * removed; call after knp_mesh_upload and before the first knp_assemble_step
+ * (KNP_E_STATE otherwise; the mode is fixed from then on).
+ *   mode 0 (default): the remark's point condition phi_e(x_e) = 0 at the reference
+ *     DOF (knp_mesh_info.pin_dof) is part of the assembled system: that DOF's row
+ *     keeps only its diagonal, its column is zero, and f_n is 0 there.
+ *   mode 1: the system is assembled without it (the remark's third way): A keeps the
+ *     constant potential as its null vector and f_n is consistent.  knp_gmres_solve
+ *     then starts every restart cycle with a coarse correction along the per-cell
+ *     constant intracellular potentials (near-null vectors of A: on them only the
+ *     membrane terms act; the correction is x += Z E^{-1} Z^T r with E = Z^T A Z, Z
+ *     one column per cell), tests the corrected residual against rtol, and at return
+ *     subtracts the reference DOF's value from every potential.  The returned x is an
+ *     approximation of the same solution as in mode 0; S and P_0 are formed the same
+ *     way.  knp_get_values and knp_apply(0/2) show the system without the condition;
+ *     knp_adjoint_solve and knp_step_vjp need mode 0 (KNP_E_STATE).
+ * KNP_E_ARG for another mode, or for mode 1 on a mesh whose cells' intracellular
+ * nodes or membrane nodes neighbour those of another cell. */
+knp_status knp_set_gauge(knp_ctx *ctx, int32_t mode);
+
 /* Build the algebraic-multigrid hierarchy of P_0 (eq. ``P_prec``), frozen for all
  * steps (same section), or with operator_step = 1 of the time-dependent P_n of the
  * most recent knp_assemble_step (the alternative that section weighs against P_0;

@@ -13,7 +13,7 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libknp.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
-HIP_SOURCES = ["assemble.hip", "assemble_p2.hip", "assemble_rows.hip", "linalg.hip", "vjp.hip"]
+HIP_SOURCES = ["assemble.hip", "assemble_p2.hip", "assemble_rows.hip", "linalg.hip", "nullspace.hip", "vjp.hip"]
 CPP_SOURCES = ["mesh.cpp", "p2.cpp", "rows.cpp", "amg.cpp", "solver.cpp", "api.cpp"]
 
 HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",

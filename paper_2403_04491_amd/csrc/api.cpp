@@ -750,18 +750,20 @@ void enqueue_assembly(knp_ctx *c, double t_n, double dt, const double *u_prev, d
     const auto p = c->phys(t_n, dt);
     const auto ma = c->mesh_args();
     const auto ga = c->gamma_args();
+    // the point condition on the reference phi_e DOF (gauge 0) or none (gauge 1)
+    const int64_t pin = c->gauge == 1 ? int64_t(-1) : h.pin_dof;
     launch::membrane_coefficients(ga, p, h.Nr[0], h.Nr[1], u_prev, gates, theta, gcoef, s);
     if (!h.walk) {   // product form: order 2, or order 1 beyond the walk kernels' limits
         auto p2_matrix_and_rhs = [&](bool force_static) {
             if (force_static || dt != c->dt_static) {
                 for (int r = 0; r < 2; ++r)
                     launch::p2_static(c->region(r), c->p2_bulk(r), p, c->d_rowptr.p, c->d_rstart.p, c->d_vals.p,
-                                      c->d_sc.p, h.pin_dof, s);
+                                      c->d_sc.p, pin, s);
                 c->dt_static = dt;
             }
             for (int r = 0; r < 2; ++r)
                 launch::p2_dynamic(c->region(r), c->p2_bulk(r), p, c->d_rowptr.p, c->d_rstart.p, c->d_vals.p,
-                                   c->d_sc.p, u_prev, f_out, h.pin_dof, s);
+                                   c->d_sc.p, u_prev, f_out, pin, s);
             launch::p2_membrane(ga, c->region(0), c->region(1), c->p2_mem(), p, c->d_rowptr.p, c->d_rstart.p,
                                 c->d_vals.p, c->d_sc.p, gcoef, f_out, s);
         };
@@ -776,12 +778,12 @@ void enqueue_assembly(knp_ctx *c, double t_n, double dt, const double *u_prev, d
         if (force_static || dt != c->dt_static) {
             for (int r = 0; r < 2; ++r)
                 launch::assemble_static(c->region(r), ma, p, c->d_rowptr.p, c->d_rstart.p, c->d_vals.p, c->d_sc.p,
-                                        h.pin_dof, s);
+                                        pin, s);
             c->dt_static = dt;
         }
         for (int r = 0; r < 2; ++r)
             launch::rows_dynamic(c->region(r), c->row_view(r), p, c->d_rowptr.p, c->d_rstart.p, c->d_vals.p,
-                                 c->d_sc.p, u_prev, f_out, h.pin_dof, s);
+                                 c->d_sc.p, u_prev, f_out, pin, s);
         launch::p2_membrane(ga, c->region(0), c->region(1), c->p2_mem(), p, c->d_rowptr.p, c->d_rstart.p,
                             c->d_vals.p, c->d_sc.p, gcoef, f_out, s);
     };
@@ -801,6 +803,7 @@ void finish_assembly(knp_ctx *c, double t_n, double dt, const double *theta) {
     c->last_dt = dt;
     c->assembled = true;
     c->T_current = false;
+    c->ns_stale = true;
 }
 
 }  // namespace
@@ -882,6 +885,19 @@ knp_status knp_assemble_step_noalloc(knp_ctx *c, double t_n, double dt, const do
     });
 }
 
+knp_status knp_set_gauge(knp_ctx *c, int32_t mode) {
+    return guarded(c, [&]() -> knp_status {
+        need_device(c);
+        if (!c->have_mesh) return fail(c, KNP_E_STATE, "knp_mesh_upload must come first");
+        if (c->assembled) return fail(c, KNP_E_STATE, "the gauge is fixed by the first knp_assemble_step");
+        if (mode != 0 && mode != 1) return fail(c, KNP_E_ARG, "gauge must be 0 or 1");
+        hip_check(hipSetDevice(c->device), "set device");
+        if (mode == 1) gauge_build(c);
+        c->gauge = mode;
+        return KNP_OK;
+    });
+}
+
 knp_status knp_amg_setup(knp_ctx *c, const knp_amg_opts *opts) {
     return guarded(c, [&]() -> knp_status {
         need_device(c);
@@ -930,6 +946,8 @@ static knp_status solve_common(knp_ctx *c, bool transpose, const double *b, doub
         if (!(o.rtol >= 0.0) || o.restart < 1 || o.restart > 4096 || o.max_it < 0 ||
             (o.precond != 0 && o.precond != 1))
             return fail(c, KNP_E_ARG, "invalid solver options");
+        if (transpose && c->gauge == 1)
+            return fail(c, KNP_E_STATE, "the adjoint solve needs gauge 0 (the point condition in the system)");
         hip_check(hipSetDevice(c->device), "set device");
         return krylov_solve(c, transpose, b, x, o, info);
     });
@@ -1032,6 +1050,7 @@ knp_status knp_step_vjp(knp_ctx *c, const double *u_prev, const double *u_n, con
         need_device(c);
         if (c->have_mesh && c->hm.order != 1) return fail(c, KNP_E_ARG, "knp_step_vjp supports order-1 meshes only");
         if (!c->assembled) return fail(c, KNP_E_STATE, "knp_assemble_step of this step must come first");
+        if (c->gauge == 1) return fail(c, KNP_E_STATE, "the step VJP needs gauge 0 (the point condition in the system)");
         if (!u_prev || !u_n || !lambda_n || !u_prev_bar) return fail(c, KNP_E_ARG, "NULL vector");
         if (c->any_hh || c->any_kir)
             return fail(c, KNP_E_ARG, "vector-Jacobian products support passive-leak membranes only");

@@ -106,6 +106,20 @@ struct knp_ctx {
     int64_t nblkT = 0;
     knp::DArray<double> d_valsT;
 
+    // gauge: 0 = the point condition phi_e = 0 at the reference DOF is part of the
+    // assembled system; 1 = the system is assembled without it and the forward solve
+    // handles the constant-potential nullspace (per-cell coarse correction, final shift)
+    int gauge = 0;
+    // gauge 1: per storage DOF the cell (0-based) whose intracellular potentials its
+    // row couples to, or -1; the intracellular potential DOFs of each cell (CSR over
+    // cells, storage indices ascending); their 1/S (ns_zs) and the same scattered into
+    // a full vector (ns_u); W = S A S u and E_k = zs_k^T W of the current system
+    int32_t ns_ncell = 0;
+    bool ns_basis = false, ns_stale = true;
+    knp::DArray<int32_t> d_ns_owner, d_ns_idx;
+    knp::DArray<int64_t> d_ns_ptr;
+    knp::DArray<double> d_ns_zs, d_ns_u, d_ns_w, d_ns_e, d_ns_sum;
+
     // preconditioner
     std::vector<double> p0_vals, near_null;
     knp::Amg amg;
@@ -206,4 +220,7 @@ knp_status krylov_solve(knp_ctx *c, bool transpose, const double *b, double *x, 
                         knp_solve_info *info);
 void ensure_transpose(knp_ctx *c);
 void apply_operator(knp_ctx *c, bool transpose, const double *x, double *y);
+// gauge 1: the cell ownership of every storage DOF and the per-cell lists of the
+// intracellular potential DOFs (host work and upload; needs the mesh)
+void gauge_build(knp_ctx *c);
 }  // namespace knp

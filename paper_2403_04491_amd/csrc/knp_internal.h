@@ -541,6 +541,19 @@ void axpby(int64_t n, double a, const double *x, double b, double *y, hipStream_
 void sub(int64_t n, const double *a, const double *b, double *y, hipStream_t s);   // y = a - b
 int reduce_blocks(int64_t n);
 
+// the constant-potential gauge inside the solver (nullspace.hip)
+// out[k] = sum_{q in [ptr[k], ptr[k+1])} zs[q] v[idx[q]], one workgroup per cell
+void cell_dot(int ncell, const int64_t *ptr, const int32_t *idx, const double *zs, const double *v, double *out,
+              hipStream_t s);
+// zs[q] = 1 / sc[int2ext[idx[q]]]; u = 0 except u[idx[q]] = zs[q]
+void cell_basis(int64_t n, int64_t nidx, const int32_t *idx, const int32_t *int2ext, const double *sc, double *zs,
+                double *u, hipStream_t s);
+// c_k = sum[k] / E[k]; r[i] -= c_owner(i) W[i], y[i] += c_owner(i) u[i] where owner(i) >= 0
+void cell_correct(int64_t n, const int32_t *owner, const double *W, const double *u, const double *sum,
+                  const double *E, double *r, double *y, hipStream_t s);
+// x[j] -= *ref on [a0, a1) and [b0, b1)
+void shift_potentials(int64_t a0, int64_t a1, int64_t b0, int64_t b1, const double *ref, double *x, hipStream_t s);
+
 // adjoint
 void vjp_bulk(const RegionArgs &ra, const MeshArgs &ma, const PhysArgs &p, const double *u_n, const double *lam,
               double *u_prev_bar, int64_t pin_dof, hipStream_t s);

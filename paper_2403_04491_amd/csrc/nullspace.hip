@@ -1,0 +1,126 @@
+// Kernels of the constant-potential gauge handled inside the solver (gauge 1; the
+// third way of removing the nullspace that the Remark on the nullspace names: the
+// system keeps its one-dimensional nullspace, the constant potential, and the Krylov
+// solve deals with it).
+//
+// Besides the exact null vector, the operator has one near-null vector per cell: a
+// constant intracellular potential on cell k, z_k.  Every bulk term of a potential or
+// concentration row is a divergence form, so A z_k (and z_k^T A) reduce to the
+// membrane terms of cell k, a capacitance-over-time-step weight times the membrane
+// mass; an error along z_k shows in the residual only at that weight.  The solver
+// therefore corrects its iterate along the z_k at the start of every cycle (a
+// Galerkin coarse correction, E = Z^T A Z diagonal because the cells' intracellular
+// DOFs do not couple), and at return shifts all potentials so that the reference
+// extracellular DOF is zero, which gives the point-condition system's solution.
+//
+// All work here is a few streaming passes; the per-cell sums are deterministic
+// (one workgroup per cell, fixed summation order).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "knp_internal.h"
+
+namespace knp {
+namespace launch {
+
+namespace {
+
+constexpr int TPB = 256;
+
+// out[k] = sum over q in [ptr[k], ptr[k+1]) of zs[q] * v[idx[q]]
+__global__ void __launch_bounds__(TPB) k_cell_dot(const int64_t *__restrict__ ptr, const int32_t *__restrict__ idx,
+                                                  const double *__restrict__ zs, const double *__restrict__ v,
+                                                  double *__restrict__ out) {
+    __shared__ double red[TPB];
+    const int k = int(blockIdx.x);
+    const int64_t a = ptr[k], b = ptr[k + 1];
+    double s = 0.0;
+    for (int64_t q = a + int64_t(threadIdx.x); q < b; q += TPB) s += zs[q] * v[idx[q]];
+    red[threadIdx.x] = s;
+    __syncthreads();
+#pragma unroll
+    for (int h = TPB / 2; h > 0; h >>= 1) {
+        if (int(threadIdx.x) < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[k] = red[0];
+}
+
+// zs[q] = 1 / S of storage DOF idx[q] (S in ABI order), and u[idx[q]] = zs[q]
+__global__ void k_cell_basis(int64_t n, const int32_t *__restrict__ idx, const int32_t *__restrict__ int2ext,
+                             const double *__restrict__ sc, double *__restrict__ zs, double *__restrict__ u) {
+    for (int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; q < n; q += int64_t(gridDim.x) * blockDim.x) {
+        const int32_t i = idx[q];
+        const double z = 1.0 / sc[int2ext[i]];
+        zs[q] = z;
+        u[i] = z;
+    }
+}
+
+__global__ void k_fill(int64_t n, double *__restrict__ y) {
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+        y[i] = 0.0;
+}
+
+// With c_k = sum[k] / E[k] (0 if E[k] is 0 or not finite): r[i] -= c_k W[i] and
+// y[i] += c_k u[i] for every storage DOF i whose rows couple to cell k (owner k >= 0)
+__global__ void k_cell_correct(int64_t n, const int32_t *__restrict__ owner, const double *__restrict__ W,
+                               const double *__restrict__ u, const double *__restrict__ sum,
+                               const double *__restrict__ E, double *__restrict__ r, double *__restrict__ y) {
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
+        const int32_t k = owner[i];
+        if (k < 0) continue;
+        const double e = E[k];
+        const double c = (e != 0.0 && isfinite(e)) ? sum[k] / e : 0.0;
+        r[i] -= c * W[i];
+        y[i] += c * u[i];
+    }
+}
+
+// x[j] -= ref for j in [a0, a1) and [b0, b1), ref = the value of x at the reference DOF,
+// copied to *ref before this kernel runs
+__global__ void k_shift(int64_t a0, int64_t a1, int64_t b0, int64_t b1, const double *__restrict__ ref,
+                        double *__restrict__ x) {
+    const double d = ref[0];
+    const int64_t na = a1 - a0, n = na + (b1 - b0);
+    for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < n; t += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t j = t < na ? a0 + t : b0 + (t - na);
+        x[j] -= d;
+    }
+}
+
+inline unsigned grid(int64_t n) {
+    int64_t g = (n + TPB - 1) / TPB;
+    if (g > 4096) g = 4096;
+    if (g < 1) g = 1;
+    return unsigned(g);
+}
+
+}  // namespace
+
+void cell_dot(int ncell, const int64_t *ptr, const int32_t *idx, const double *zs, const double *v, double *out,
+              hipStream_t s) {
+    if (ncell <= 0) return;
+    hipLaunchKernelGGL(k_cell_dot, dim3(unsigned(ncell)), dim3(TPB), 0, s, ptr, idx, zs, v, out);
+}
+
+void cell_basis(int64_t n, int64_t nidx, const int32_t *idx, const int32_t *int2ext, const double *sc, double *zs,
+                double *u, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill, dim3(grid(n)), dim3(TPB), 0, s, n, u);
+    if (nidx > 0) hipLaunchKernelGGL(k_cell_basis, dim3(grid(nidx)), dim3(TPB), 0, s, nidx, idx, int2ext, sc, zs, u);
+}
+
+void cell_correct(int64_t n, const int32_t *owner, const double *W, const double *u, const double *sum,
+                  const double *E, double *r, double *y, hipStream_t s) {
+    hipLaunchKernelGGL(k_cell_correct, dim3(grid(n)), dim3(TPB), 0, s, n, owner, W, u, sum, E, r, y);
+}
+
+void shift_potentials(int64_t a0, int64_t a1, int64_t b0, int64_t b1, const double *ref, double *x, hipStream_t s) {
+    const int64_t n = (a1 - a0) + (b1 - b0);
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_shift, dim3(grid(n)), dim3(TPB), 0, s, a0, a1, b0, b1, ref, x);
+}
+
+}  // namespace launch
+}  // namespace knp

@@ -10,6 +10,13 @@
 // FP64 and the FP32 V-cycle.  Arnoldi, the Hessenberg least-squares problem,
 // the solution update and the true-residual recomputation are FP64.
 // One device-to-host copy of the new Hessenberg column per iteration.
+//
+// With gauge 1 the system carries no point condition and keeps the constant
+// potential as its null vector (consistent right-hand side); the forward solve
+// then applies, at the start of every cycle, the per-cell coarse correction of
+// nullspace.hip to the iterate and its residual, so that the stopping test sees the
+// corrected residual, and at return shifts every potential so that the reference
+// extracellular DOF is zero: the solution of the point-condition system.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -51,7 +58,87 @@ void ensure_workspace(knp_ctx *c, int m, bool z32) {
     c->z32 = z32;
 }
 
+// gauge 1: 1/S on each cell's intracellular potential DOFs (once; S is fixed at the
+// first assembly), then W = S A S u and E for the current system (after every assembly)
+void gauge_refresh(knp_ctx *c) {
+    const int64_t N = c->hm.N;
+    hipStream_t s = c->stream;
+    if (!c->ns_basis) {
+        const int64_t nidx = int64_t(c->d_ns_idx.n);
+        c->d_ns_zs.alloc(size_t(nidx));
+        c->d_ns_u.alloc(size_t(N));
+        c->d_ns_w.alloc(size_t(N));
+        c->d_ns_e.alloc(size_t(c->ns_ncell));
+        c->d_ns_sum.alloc(size_t(c->ns_ncell));
+        launch::cell_basis(N, nidx, c->d_ns_idx.p, c->d_int2ext.p, c->d_sc.p, c->d_ns_zs.p, c->d_ns_u.p, s);
+        c->ns_basis = true;
+        c->ns_stale = true;
+    }
+    if (c->ns_stale) {
+        apply_operator(c, false, c->d_ns_u.p, c->d_ns_w.p);
+        launch::cell_dot(c->ns_ncell, c->d_ns_ptr.p, c->d_ns_idx.p, c->d_ns_zs.p, c->d_ns_w.p, c->d_ns_e.p, s);
+        c->ns_stale = false;
+    }
+}
+
 }  // namespace
+
+void gauge_build(knp_ctx *c) {
+    const HostMesh &h = c->hm;
+    const int64_t N = h.N, Ni = h.Nr[0], Ne = h.Nr[1];
+    const int K = h.n_cells;
+    if (K < 1) throw Error{KNP_E_ARG, "gauge 1 needs at least one cell"};
+    // the cells' intracellular DOFs must not couple: every region neighbour of an
+    // intracellular node and every membrane neighbour of a membrane node lies in its cell
+    for (int64_t l = 0; l < Ni; ++l) {
+        const int32_t cl = h.vcell[h.verts[0][l]];
+        for (int64_t q = h.prow[0][l]; q < h.prow[0][l + 1]; ++q)
+            if (h.vcell[h.verts[0][h.pcol[0][q]]] != cl)
+                throw Error{KNP_E_ARG, "gauge 1 needs cells whose intracellular nodes do not neighbour each other"};
+    }
+    for (size_t g = 0; g < h.gamma.size(); ++g) {
+        const int32_t cl = h.vcell[h.gamma[g]];
+        for (int64_t q = h.grow[g]; q < h.grow[g + 1]; ++q)
+            if (h.vcell[h.gcol[q]] != cl)
+                throw Error{KNP_E_ARG, "gauge 1 needs cells whose membranes do not neighbour each other"};
+    }
+    // owner of each storage DOF: the cell of its intracellular node, or of its
+    // extracellular node when that node is on the membrane; -1 otherwise
+    std::vector<int32_t> owner(N, -1);
+    std::vector<int64_t> ptr(size_t(K) + 1, 0);
+    for (int64_t i = 0; i < N; ++i) {
+        const int64_t e = c->int2ext[i];
+        int32_t cell;
+        if (e < 4 * Ni) {
+            cell = h.vcell[h.verts[0][e % Ni]];
+        } else {
+            const int32_t v = h.verts[1][(e - 4 * Ni) % Ne];
+            cell = h.gidx[v] >= 0 ? h.vcell[v] : 0;
+        }
+        if (cell < 0 || cell > K) throw Error{KNP_E_ARG, "internal: cell id out of range"};
+        owner[i] = cell - 1;
+        if (e >= 3 * Ni && e < 4 * Ni) ++ptr[cell];
+    }
+    for (int k = 0; k < K; ++k) ptr[k + 1] += ptr[k];
+    std::vector<int32_t> idx(size_t(ptr[K]));
+    {
+        std::vector<int64_t> fill(ptr.begin(), ptr.end() - 1);
+        for (int64_t i = 0; i < N; ++i) {
+            const int64_t e = c->int2ext[i];
+            if (e >= 3 * Ni && e < 4 * Ni) idx[size_t(fill[owner[i]]++)] = int32_t(i);
+        }
+    }
+    hipStream_t s = c->stream;
+    c->d_ns_owner.alloc(size_t(N));
+    c->d_ns_owner.upload(owner, s);
+    c->d_ns_ptr.alloc(ptr.size());
+    c->d_ns_ptr.upload(ptr, s);
+    c->d_ns_idx.alloc(idx.size());
+    c->d_ns_idx.upload(idx, s);
+    c->ns_ncell = K;
+    c->ns_basis = false;
+    c->ns_stale = true;
+}
 
 void apply_operator(knp_ctx *c, bool transpose, const double *x, double *y) {
     const int64_t N = c->hm.N;
@@ -91,6 +178,8 @@ knp_status krylov_solve(knp_ctx *c, bool transpose, const double *b, double *x, 
         if (info) *info = inf;
         return KNP_OK;
     }
+    const bool gauge = c->gauge == 1 && !transpose;
+    if (gauge) gauge_refresh(c);
     std::vector<double> H(size_t(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
     auto Hc = [&](int i, int j) -> double & { return H[size_t(j) * (m + 1) + i]; };
     int its = 0, restarts = 0;
@@ -110,6 +199,10 @@ knp_status krylov_solve(knp_ctx *c, bool transpose, const double *b, double *x, 
     while (true) {
         apply_operator(c, transpose, yh, w);
         launch::sub(N, bh, w, w, s);
+        if (gauge) {   // yh += sum_k c_k S^{-1} z_k, S r -= sum_k c_k S A z_k
+            launch::cell_dot(c->ns_ncell, c->d_ns_ptr.p, c->d_ns_idx.p, c->d_ns_zs.p, w, c->d_ns_sum.p, s);
+            launch::cell_correct(N, c->d_ns_owner.p, c->d_ns_w.p, c->d_ns_u.p, c->d_ns_sum.p, c->d_ns_e.p, w, yh, s);
+        }
         const double beta = std::sqrt(dev_dot(c, w, w, N));
         if (!std::isfinite(beta)) throw Error{KNP_E_NUMERIC, "NaN or Inf in the residual"};
         est = beta / bnorm;
@@ -217,6 +310,12 @@ knp_status krylov_solve(knp_ctx *c, bool transpose, const double *b, double *x, 
     inf.its = its;
     inf.restarts = restarts;
     launch::to_external(N, c->d_int2ext.p, yh, c->d_sc.p, x, 0, s);   // x = S yh
+    if (gauge) {   // every potential minus the reference DOF's value
+        const int64_t Ni = c->hm.Nr[0], Ne = c->hm.Nr[1];
+        hip_check(hipMemcpyAsync(c->d_ns_sum.p, x + c->hm.pin_dof, sizeof(double), hipMemcpyDeviceToDevice, s),
+                  "reference potential");
+        launch::shift_potentials(3 * Ni, 4 * Ni, 4 * Ni + 3 * Ne, 4 * Ni + 4 * Ne, c->d_ns_sum.p, x, s);
+    }
     hip_check(hipStreamSynchronize(s), "solve sync");
     c->tm.harvest();
     if (info) *info = inf;

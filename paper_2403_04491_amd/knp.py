@@ -22,7 +22,8 @@ EXPORTS = ["knp_create", "knp_destroy", "knp_last_error", "knp_mesh_upload", "kn
            "knp_get_gamma", "knp_set_params", "knp_assemble_step", "knp_assemble_step_noalloc", "knp_amg_setup",
            "knp_mesh_upload_p2", "knp_get_edges",
            "knp_gmres_solve", "knp_adjoint_solve", "knp_step_vjp", "knp_apply",
-           "knp_get_scaling", "knp_get_values", "knp_timing", "knp_timing_read", "knp_amg_stats"]
+           "knp_get_scaling", "knp_get_values", "knp_timing", "knp_timing_read", "knp_amg_stats",
+           "knp_set_gauge"]
 TIMERS = ["spmv_A", "cheb_L0", "resid_L0", "vcycle", "assembly"]
 
 
@@ -97,6 +98,7 @@ def load_library(path: str = _LIB_PATH) -> C.CDLL:
     lib.knp_assemble_step.argtypes = [P, D, D, P, P, P, P]
     lib.knp_assemble_step_noalloc.argtypes = [P, D, D, P, P, P, P]
     lib.knp_amg_setup.argtypes = [P, C.POINTER(AmgOpts)]
+    lib.knp_set_gauge.argtypes = [P, C.c_int32]
     lib.knp_gmres_solve.argtypes = [P, P, P, C.POINTER(SolveOpts), C.POINTER(SolveInfo)]
     lib.knp_adjoint_solve.argtypes = [P, P, P, C.POINTER(SolveOpts), C.POINTER(SolveInfo)]
     lib.knp_step_vjp.argtypes = [P, P, P, P, P, P]
@@ -261,6 +263,11 @@ class Context:
             _dptr(gates, torch.float64, 3 * self.info.n_gamma) if gates is not None else None,
             _dptr(theta, torch.float64, self.info.n_cells) if theta is not None else None,
             _dptr(f_out, torch.float64, N)))
+
+    def set_gauge(self, mode: int):
+        """knp_set_gauge: 0 = point condition on the reference phi_e DOF in the system;
+        1 = system without it, nullspace handled by the forward solve."""
+        self._check(self._lib.knp_set_gauge(self._c, int(mode)))
 
     def amg_setup(self, opts: AmgOpts | None = None):
         self._check(self._lib.knp_amg_setup(self._c, C.byref(opts) if opts is not None else None))

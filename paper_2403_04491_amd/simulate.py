@@ -29,13 +29,18 @@ def initial_vector(case, dof_vertex, info, edges=None):
 class KnpSolver:
     """Holds one context and the state (u, gates) of a run on one GPU."""
 
-    def __init__(self, case, device=0, amg=None, solve=None, theta=None, order=1):
-        """case: a vertex mesh with per-vertex data; order 2 adds the edge nodes (P2)."""
+    def __init__(self, case, device=0, amg=None, solve=None, theta=None, order=1, gauge=0):
+        """case: a vertex mesh with per-vertex data; order 2 adds the edge nodes (P2);
+        gauge: 0 = point condition on phi_e in the system, 1 = nullspace handled by the
+        solve (knp_set_gauge)."""
         self.case = case
         self.order = order
+        self.gauge = gauge
         self.dev = torch.device("cuda", device)
         self.ctx = Context(device)
         self.info = self.ctx.mesh_upload(case.dim, case.xyz, case.elem, case.tag, case.pin_vertex, order=order)
+        if gauge:
+            self.ctx.set_gauge(gauge)
         self.ctx.set_params(case.params, case.cell_model, case.cell_stim)
         self.rowptr, self.colidx, self.dof_vertex = self.ctx.get_layout()
         self.gamma = self.ctx.get_gamma()

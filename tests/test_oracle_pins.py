@@ -180,6 +180,52 @@ def test_nullspace_unpinned(which, request):
     assert abs(e @ s.f) <= 1e-13 * np.abs(s.f * e).sum()
 
 
+def test_cell_potential_near_null_vectors():
+    """The constant intracellular potential of one cell, z_k, is a near-null vector of the
+    operator from both sides: every bulk term of a row is a divergence form, so A z_k and
+    z_k^T A keep only the membrane terms of cell k (the capacitive weight C_m/F times the
+    membrane mass, eq. ``weak_disc``), and z_k^T A z_j is 0 for j != k and C_m/F times the
+    membrane area of cell k for j = k.  The area is the closed form 2(ab + bc + ca) of the
+    grid-aligned box cell, from the extent of its intracellular vertices."""
+    case = config_case(3, per_pitch=4)
+    asm = Assembler(case)
+    lay = asm.lay
+    Ni, Ne = lay.N_r
+    u = initial_state(case, lay)
+    s = asm.assemble(u, initial_gates(case, lay), case.dt, case.dt, pin=False)
+    A = s.csr()
+    absA = abs(A)
+    Vi, Ve = np.asarray(lay.verts[0]), np.asarray(lay.verts[1])
+    cell_i = lay.vert_cell[Vi]
+    on_gamma = np.zeros(lay.n_vert, bool)
+    on_gamma[lay.gamma] = True
+    # cell of every DOF's vertex when that vertex is on the membrane, else 0
+    dof_cell = np.zeros(lay.N, np.int64)
+    for f in range(4):
+        dof_cell[f * Ni:(f + 1) * Ni] = np.where(on_gamma[Vi], cell_i, 0)
+        dof_cell[4 * Ni + f * Ne:4 * Ni + (f + 1) * Ne] = np.where(on_gamma[Ve], lay.vert_cell[Ve], 0)
+    cells = np.unique(cell_i[cell_i > 0])
+    assert len(cells) == 64
+    Z = np.zeros((lay.N, len(cells)))
+    for j, k in enumerate(cells):
+        Z[3 * Ni + np.nonzero(cell_i == k)[0], j] = 1.0
+    AZ, ZA = A @ Z, (A.T @ Z)
+    scale_r, scale_c = (absA @ Z).max(), (absA.T @ Z).max()
+    E = Z.T @ AZ
+    Eabs = Z.T @ (absA @ Z)     # the scale of the rounding in E (the stiffness sums cancel)
+    Cm_F = case.params["C_m"] / case.params["F"]
+    for j, k in enumerate(cells):
+        off = dof_cell != k
+        assert np.abs(AZ[off, j]).max() <= 1e-13 * scale_r
+        assert np.abs(ZA[off, j]).max() <= 1e-13 * scale_c
+        assert np.abs(AZ[~off, j]).max() > 1e-6 * scale_r
+        ext = np.ptp(case.xyz[Vi[cell_i == k]], axis=0)
+        area = 2.0 * (ext[0] * ext[1] + ext[1] * ext[2] + ext[2] * ext[0])
+        assert abs(E[j, j] - Cm_F * area) <= 1e-13 * Eabs[j, j]
+    off_diag = E - np.diag(np.diag(E))
+    assert np.abs(off_diag).max() <= 1e-13 * Eabs.max()
+
+
 def _mass(case, lay, r):
     rr, cc, vv = bulk_coo(case, lay, r, kind="mass")
     return sp.coo_matrix((vv, (rr, cc)), shape=(lay.N_r[r],) * 2).tocsr()
