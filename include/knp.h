@@ -316,7 +316,8 @@ enum { KNP_TIMER_SPMV_A = 0,        /* y = (S A S) x, Krylov operator          *
        KNP_TIMER_RESID_L0 = 2,      /* residual on the finest AMG level        */
        KNP_TIMER_VCYCLE = 3,        /* one whole V-cycle                        */
        KNP_TIMER_ASSEMBLY = 4,      /* knp_assemble_step device work            */
-       KNP_TIMER_COUNT = 5 };
+       KNP_TIMER_RESID_A = 5,       /* y = (S A S) x for the solver's true residuals (FP64 x) */
+       KNP_TIMER_COUNT = 6 };
 typedef struct {
     int64_t launches;
     double total_ms;

@@ -113,10 +113,12 @@ struct knp_ctx {
     // gauge 1: per storage DOF the cell (0-based) whose intracellular potentials its
     // row couples to, or -1; the intracellular potential DOFs of each cell (CSR over
     // cells, storage indices ascending); their 1/S (ns_zs) and the same scattered into
-    // a full vector (ns_u); W = S A S u and E_k = zs_k^T W of the current system
+    // a full vector (ns_u); W = S A S u (computed on the membrane rows, 0 elsewhere) and
+    // E_k = zs_k^T W of the current system
     int32_t ns_ncell = 0;
     bool ns_basis = false, ns_stale = true;
-    knp::DArray<int32_t> d_ns_owner, d_ns_idx;
+    int64_t ns_nrows = 0;   // storage rows of membrane nodes (the rows W is computed on)
+    knp::DArray<int32_t> d_ns_owner, d_ns_idx, d_ns_rows;
     knp::DArray<int64_t> d_ns_ptr;
     knp::DArray<double> d_ns_zs, d_ns_u, d_ns_w, d_ns_e, d_ns_sum;
 
@@ -219,7 +221,8 @@ namespace knp {
 knp_status krylov_solve(knp_ctx *c, bool transpose, const double *b, double *x, const knp_solve_opts &o,
                         knp_solve_info *info);
 void ensure_transpose(knp_ctx *c);
-void apply_operator(knp_ctx *c, bool transpose, const double *x, double *y);
+// y = (S A S) x or its transpose, FP64; timed under `timer` (a KNP_TIMER_* class)
+void apply_operator(knp_ctx *c, bool transpose, const double *x, double *y, int timer = KNP_TIMER_SPMV_A);
 // gauge 1: the cell ownership of every storage DOF and the per-cell lists of the
 // intracellular potential DOFs (host work and upload; needs the mesh)
 void gauge_build(knp_ctx *c);

@@ -551,6 +551,10 @@ void cell_basis(int64_t n, int64_t nidx, const int32_t *idx, const int32_t *int2
 // c_k = sum[k] / E[k]; r[i] -= c_owner(i) W[i], y[i] += c_owner(i) u[i] where owner(i) >= 0
 void cell_correct(int64_t n, const int32_t *owner, const double *W, const double *u, const double *sum,
                   const double *E, double *r, double *y, hipStream_t s);
+// y[rows[t]] = (A x)[rows[t]] for the listed storage rows (CSR storage view), others untouched
+void rows_spmv(int64_t n, const int32_t *rows, const int64_t *rowptr, const int32_t *col, const double *val,
+               const double *x, double *y, hipStream_t s);
+void fill_zero(int64_t n, double *y, hipStream_t s);
 // x[j] -= *ref on [a0, a1) and [b0, b1)
 void shift_potentials(int64_t a0, int64_t a1, int64_t b0, int64_t b1, const double *ref, double *x, hipStream_t s);
 

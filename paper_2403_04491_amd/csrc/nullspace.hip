@@ -6,8 +6,9 @@
 // Besides the exact null vector, the operator has one near-null vector per cell: a
 // constant intracellular potential on cell k, z_k.  Every bulk term of a potential or
 // concentration row is a divergence form, so A z_k (and z_k^T A) reduce to the
-// membrane terms of cell k, a capacitance-over-time-step weight times the membrane
-// mass; an error along z_k shows in the residual only at that weight.  The solver
+// membrane terms of cell k, the capacitive weight C_m/F times the membrane mass (and
+// the ions' shares of it in the concentration rows); an error along z_k shows in the
+// residual only at that weight.  The solver
 // therefore corrects its iterate along the z_k at the start of every cycle (a
 // Galerkin coarse correction, E = Z^T A Z diagonal because the cells' intracellular
 // DOFs do not couple), and at return shifts all potentials so that the reference
@@ -90,6 +91,27 @@ __global__ void k_shift(int64_t a0, int64_t a1, int64_t b0, int64_t b1, const do
     }
 }
 
+// y[rows[t]] = the row's stored entries times x; 16 lanes per listed row (rows hold a
+// few dozen entries), fixed order: lane-strided partial sums, then a butterfly
+constexpr int RL = 16;
+__global__ void __launch_bounds__(TPB) k_rows_spmv(int64_t n, const int32_t *__restrict__ rows,
+                                                   const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+                                                   const double *__restrict__ val, const double *__restrict__ x,
+                                                   double *__restrict__ y) {
+    const int64_t t = (int64_t(blockIdx.x) * TPB + threadIdx.x) / RL;
+    const int lane = int(threadIdx.x % RL);
+    double s = 0.0;
+    int32_t r = -1;
+    if (t < n) {
+        r = rows[t];
+        const int64_t a = rowptr[r], b = rowptr[r + 1];
+        for (int64_t q = a + lane; q < b; q += RL) s += val[q] * x[col[q]];
+    }
+#pragma unroll
+    for (int off = RL / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, RL);
+    if (lane == 0 && r >= 0) y[r] = s;
+}
+
 inline unsigned grid(int64_t n) {
     int64_t g = (n + TPB - 1) / TPB;
     if (g > 4096) g = 4096;
@@ -109,6 +131,17 @@ void cell_basis(int64_t n, int64_t nidx, const int32_t *idx, const int32_t *int2
                 double *u, hipStream_t s) {
     hipLaunchKernelGGL(k_fill, dim3(grid(n)), dim3(TPB), 0, s, n, u);
     if (nidx > 0) hipLaunchKernelGGL(k_cell_basis, dim3(grid(nidx)), dim3(TPB), 0, s, nidx, idx, int2ext, sc, zs, u);
+}
+
+void rows_spmv(int64_t n, const int32_t *rows, const int64_t *rowptr, const int32_t *col, const double *val,
+               const double *x, double *y, hipStream_t s) {
+    if (n <= 0) return;
+    const int64_t nb = (n * RL + TPB - 1) / TPB;
+    hipLaunchKernelGGL(k_rows_spmv, dim3(unsigned(nb)), dim3(TPB), 0, s, n, rows, rowptr, col, val, x, y);
+}
+
+void fill_zero(int64_t n, double *y, hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(k_fill, dim3(grid(n)), dim3(TPB), 0, s, n, y);
 }
 
 void cell_correct(int64_t n, const int32_t *owner, const double *W, const double *u, const double *sum,

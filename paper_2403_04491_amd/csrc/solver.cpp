@@ -71,11 +71,14 @@ void gauge_refresh(knp_ctx *c) {
         c->d_ns_e.alloc(size_t(c->ns_ncell));
         c->d_ns_sum.alloc(size_t(c->ns_ncell));
         launch::cell_basis(N, nidx, c->d_ns_idx.p, c->d_int2ext.p, c->d_sc.p, c->d_ns_zs.p, c->d_ns_u.p, s);
+        launch::fill_zero(N, c->d_ns_w.p, s);
         c->ns_basis = true;
         c->ns_stale = true;
     }
     if (c->ns_stale) {
-        apply_operator(c, false, c->d_ns_u.p, c->d_ns_w.p);
+        // W on the membrane rows; the rest of W stays 0 (A z_k vanishes there)
+        launch::rows_spmv(c->ns_nrows, c->d_ns_rows.p, c->d_rowptr_s.p, c->d_colidx.p, c->d_vals.p, c->d_ns_u.p,
+                          c->d_ns_w.p, s);
         launch::cell_dot(c->ns_ncell, c->d_ns_ptr.p, c->d_ns_idx.p, c->d_ns_zs.p, c->d_ns_w.p, c->d_ns_e.p, s);
         c->ns_stale = false;
     }
@@ -120,6 +123,14 @@ void gauge_build(knp_ctx *c) {
         if (e >= 3 * Ni && e < 4 * Ni) ++ptr[cell];
     }
     for (int k = 0; k < K; ++k) ptr[k + 1] += ptr[k];
+    // the rows of membrane nodes (both regions): elsewhere every term of a row that
+    // meets z_k is a divergence form, so (A z_k)_i is 0 up to rounding and W_i is kept 0
+    std::vector<int32_t> rows;
+    for (int64_t i = 0; i < N; ++i) {
+        const int64_t e = c->int2ext[i];
+        const int32_t v = e < 4 * Ni ? h.verts[0][e % Ni] : h.verts[1][(e - 4 * Ni) % Ne];
+        if (owner[i] >= 0 && h.gidx[v] >= 0) rows.push_back(int32_t(i));
+    }
     std::vector<int32_t> idx(size_t(ptr[K]));
     {
         std::vector<int64_t> fill(ptr.begin(), ptr.end() - 1);
@@ -135,24 +146,27 @@ void gauge_build(knp_ctx *c) {
     c->d_ns_ptr.upload(ptr, s);
     c->d_ns_idx.alloc(idx.size());
     c->d_ns_idx.upload(idx, s);
+    c->d_ns_rows.alloc(rows.size());
+    c->d_ns_rows.upload(rows, s);
+    c->ns_nrows = int64_t(rows.size());
     c->ns_ncell = K;
     c->ns_basis = false;
     c->ns_stale = true;
 }
 
-void apply_operator(knp_ctx *c, bool transpose, const double *x, double *y) {
+void apply_operator(knp_ctx *c, bool transpose, const double *x, double *y, int timer) {
     const int64_t N = c->hm.N;
-    hipEvent_t t0 = c->tm.begin(KNP_TIMER_SPMV_A, c->stream);
+    hipEvent_t t0 = c->tm.begin(timer, c->stream);
     if (transpose) {
         launch::spmv<double, double, double>(c->viewT(), c->d_valsT.p, x, y, c->stream);
     } else if (c->vtx) {
         launch::spmv_vtx<double>(c->viewV(), c->d_vals.p, x, y, c->stream);
-        c->tm.end(KNP_TIMER_SPMV_A, t0, c->vtx_bytes(8.0), c->stream);
+        c->tm.end(timer, t0, c->vtx_bytes(8.0), c->stream);
         return;
     } else {
         launch::spmv<double, double, double>(c->viewA(), c->d_vals.p, x, y, c->stream);
     }
-    c->tm.end(KNP_TIMER_SPMV_A, t0, 12.0 * double(c->hm.nnz) + 32.0 * double(N) + 8.0, c->stream);
+    c->tm.end(timer, t0, 12.0 * double(c->hm.nnz) + 32.0 * double(N) + 8.0, c->stream);
 }
 
 knp_status krylov_solve(knp_ctx *c, bool transpose, const double *b, double *x, const knp_solve_opts &o,
@@ -197,7 +211,7 @@ knp_status krylov_solve(knp_ctx *c, bool transpose, const double *b, double *x, 
     // every exit below happens right after the residual of the current iterate is
     // recomputed, so that residual is the one reported
     while (true) {
-        apply_operator(c, transpose, yh, w);
+        apply_operator(c, transpose, yh, w, KNP_TIMER_RESID_A);
         launch::sub(N, bh, w, w, s);
         if (gauge) {   // yh += sum_k c_k S^{-1} z_k, S r -= sum_k c_k S A z_k
             launch::cell_dot(c->ns_ncell, c->d_ns_ptr.p, c->d_ns_idx.p, c->d_ns_zs.p, w, c->d_ns_sum.p, s);

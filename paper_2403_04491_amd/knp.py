@@ -24,7 +24,7 @@ EXPORTS = ["knp_create", "knp_destroy", "knp_last_error", "knp_mesh_upload", "kn
            "knp_gmres_solve", "knp_adjoint_solve", "knp_step_vjp", "knp_apply",
            "knp_get_scaling", "knp_get_values", "knp_timing", "knp_timing_read", "knp_amg_stats",
            "knp_set_gauge"]
-TIMERS = ["spmv_A", "cheb_L0", "resid_L0", "vcycle", "assembly"]
+TIMERS = ["spmv_A", "cheb_L0", "resid_L0", "vcycle", "assembly", "resid_A"]
 
 
 class KnpError(RuntimeError):
