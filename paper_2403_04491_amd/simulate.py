@@ -26,6 +26,16 @@ def initial_vector(case, dof_vertex, info, edges=None):
     return u0
 
 
+# AMG settings swept on the 132^3 lattice (steps 6-25, FP32 levels) in each gauge (the
+# other options keep the library's defaults).  With the point condition (gauge 0) the
+# per-cell potential modes keep the iteration count up and a cheap cycle wins; with the
+# nullspace handled by the solve (gauge 1) more smoothing on the coarser levels pays.
+AMG_BY_GAUGE = {
+    0: dict(cheb_degree=5, cheb_ratio=2.5, coarse_drop=0.01, coarse_post_degree=1),
+    1: dict(cheb_degree=3, cheb_ratio=3.5, coarse_drop=0.02, coarse_post_degree=4),
+}
+
+
 class KnpSolver:
     """Holds one context and the state (u, gates) of a run on one GPU."""
 
