@@ -323,7 +323,8 @@ def model_a_bench(args, log):
 
     def run(nx, membrane, n_steps, timed):
         case = model_a_evolution_case(nx=nx, membrane=membrane, n_steps=n_steps)
-        s = KnpSolver(case, gauge=args.gauge, amg=amg_opts(precision=1, **ma_amg),
+        s = KnpSolver(case, gauge=args.gauge, extrapolate=args.initial_guess == "extrap",
+                      amg=amg_opts(precision=1, **ma_amg),
                       solve=solve_opts(rtol=1e-6, restart=30, max_it=2000), order=order)
         ri, re = s.membrane_rows()
         trace = torch.empty((n_steps + 1, ri.numel()), dtype=torch.float64, device=s.dev)
@@ -387,7 +388,8 @@ def model_a_bench(args, log):
         # the time-dependent P_n: the hierarchy rebuilt from every step's matrix
         m = min(args.ma_pn_steps, n_steps)
         case_n = model_a_evolution_case(nx=nx, membrane="hh", n_steps=m)
-        sn = KnpSolver(case_n, gauge=args.gauge, amg=amg_opts(precision=1, operator_step=1, **ma_amg),
+        sn = KnpSolver(case_n, gauge=args.gauge, extrapolate=args.initial_guess == "extrap",
+                       amg=amg_opts(precision=1, operator_step=1, **ma_amg),
                        solve=solve_opts(rtol=1e-6, restart=30, max_it=2000), order=order)
         its_n, t_n = [], []
         for n in range(1, m + 1):
@@ -437,7 +439,7 @@ def model_a_bench(args, log):
                                f"the periodic Na stimulus on Gamma, uniform initial data, dt=0.1 ms, {n_steps} steps, "
                                f"FGMRES(30) + AMG(P_0) FP32 levels, rtol 1e-6",
                    "N": s.info.N, "nnz_A": s.info.nnz_A, "parallelism": "1 GPU", "gauge": args.gauge,
-                   "amg": ma_amg},
+                   "initial_guess": args.initial_guess, "amg": ma_amg},
         "first_step_s": round(t_first, 3),
         "ms_per_step_max": round(1e3 * times.max(), 3),
         "its_per_step": {"min": int(its[1:].min()), "max": int(its[1:].max()), "mean": round(float(its[1:].mean()), 3),
@@ -480,7 +482,8 @@ def config2_bench(args, log):
     for prec in (0, 1):
         name = "fp64" if prec == 0 else "fp32_amg"
         case = config_case(2)
-        s = KnpSolver(case, gauge=args.gauge, amg=amg_opts(precision=prec, **amg_flags(args)),
+        s = KnpSolver(case, gauge=args.gauge, extrapolate=args.initial_guess == "extrap",
+                      amg=amg_opts(precision=prec, **amg_flags(args)),
                       solve=solve_opts(rtol=1e-6, restart=30, max_it=4000))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -532,7 +535,7 @@ def config2_bench(args, log):
         "data": "synthetic", "vs_baseline": None,
         "config": {"workload": "3D Model A: [0,1]^3 um, one cell [0.25,0.75]^3, 32^3 x 6 tets, N=149,900, "
                                "Hodgkin-Huxley with the stimulus, dt=0.05 ms, 100 steps, FGMRES(30) rtol 1e-6",
-                   "gauge": args.gauge},
+                   "gauge": args.gauge, "initial_guess": args.initial_guess},
         "by_precision": runs,
     }
     print(json.dumps(out), flush=True)
@@ -546,6 +549,7 @@ def adjoint_bench(args, log):
     import numpy as np
     import torch
     from knp_inputs import config_case
+    from paper_2403_04491_amd import amg_opts
     from paper_2403_04491_amd.adjoint import AdjointProblem
 
     case = config_case(4, per_pitch=args.adj_per_pitch, n_steps=args.adj_steps)
@@ -558,7 +562,7 @@ def adjoint_bench(args, log):
 
     def timed_gradient(rtol, adj_rtol):
         prob = AdjointProblem(case, every=args.adj_every, rtol=rtol, adj_rtol=adj_rtol, restart=args.adj_restart,
-                              progress=progress, max_it=8000)
+                              progress=progress, max_it=8000, amg=amg_opts(**amg_flags(args)))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         J, ckpt = prob.forward(theta)
@@ -622,7 +626,7 @@ def adjoint_bench(args, log):
         "config": {"workload": f"2x2x2 lattice of jittered box cells, {case.shape[0]}^3 grid x 6 tets, "
                                f"N={prob.solver.info.N} unknowns, 8 passive-leak cells with log-uniform leak factors, "
                                f"16 probes, dt=0.05 ms, {n_full} steps, checkpoints every {args.adj_every}",
-                   "N": prob.solver.info.N, "n_cells": len(case.theta)},
+                   "N": prob.solver.info.N, "n_cells": len(case.theta), "gauge": 0, "amg": amg_flags(args)},
         "timed": {"steps": n_full, "forward_rtol": args.adj_rtol_fwd, "adjoint_rtol": args.adj_rtol_adj,
                   **t_fast, "J": J_fast, "gradient": [float(v) for v in g_fast]},
         "check": {"steps": case.n_steps, "forward_rtol": args.fd_rtol_fwd, "adjoint_rtol": args.fd_rtol_adj,
@@ -660,7 +664,8 @@ def large_bench(args, log):
     log(f"case {case.name}: {case.n_vert} vertices, {case.n_elem} tets, generated in {time.perf_counter() - t0:.1f} s")
     sample("start")
     t0 = time.perf_counter()
-    solver = KnpSolver(case, gauge=args.gauge, amg=amg_opts(precision=1, **amg_flags(args)),
+    solver = KnpSolver(case, gauge=args.gauge, extrapolate=args.initial_guess == "extrap",
+                       amg=amg_opts(precision=1, **amg_flags(args)),
                        solve=solve_opts(rtol=1e-6, restart=30, max_it=2000))
     torch.cuda.synchronize()
     t_upload = time.perf_counter() - t0
@@ -727,7 +732,8 @@ def large_bench(args, log):
         "config": {"workload": f"8x8x8 lattice of 4:1:1 jittered box cells, {case.shape[0]}x{case.shape[1]}x"
                                f"{case.shape[2]} grid x 6 tets, N={info.N} unknowns, passive leak, dt=0.05 ms, "
                                f"FGMRES(30) rtol 1e-6",
-                   "N": info.N, "nnz_A": info.nnz_A, "nnz_P0": info.nnz_P0, "gauge": args.gauge},
+                   "N": info.N, "nnz_A": info.nnz_A, "nnz_P0": info.nnz_P0, "gauge": args.gauge,
+                   "initial_guess": args.initial_guess},
         "its_per_step": its, "step_ms": [round(t * 1e3, 1) for t in times],
         "first_step": {"restart": args.large_first_restart, "its": inf1.its, "rel_res": inf1.rel_res,
                        "converged": ok1, "s": round(t_first, 2),
@@ -760,6 +766,11 @@ def main():
     ap.add_argument("--first-restart", type=int, default=200,
                     help="FGMRES restart of the untimed first step (later steps: 30)")
     ap.add_argument("--restart", type=int, default=30)
+    ap.add_argument("--initial-guess", choices=["prev", "extrap"], default=None,
+                    help="start of each step's solve: u_{n-1} (the paper's) or 2 u_{n-1} - u_{n-2} "
+                         "(knp_extrapolate) once two steps are known; default extrap, except prev "
+                         "for --config2, whose 3D action potential the extrapolation overshoots "
+                         "(up to 500 iterations in a step)")
     ap.add_argument("--gauge", type=int, default=1, choices=[0, 1],
                     help="0: point condition on phi_e in the system; 1: system without it, the "
                          "constant-potential nullspace handled by the solve (knp_set_gauge)")
@@ -815,6 +826,10 @@ def main():
     ap.add_argument("--fd-rtol-fwd", type=float, default=1e-11)
     ap.add_argument("--fd-rtol-adj", type=float, default=1e-8)
     args = ap.parse_args()
+    if args.initial_guess is None:
+        args.initial_guess = "prev" if args.config2 else "extrap"
+    if args.adjoint:
+        args.gauge = 0   # the adjoint solve and the VJPs need the point condition
     from paper_2403_04491_amd.simulate import AMG_BY_GAUGE   # 93 against 58 steps/s (gauge 1)
     for k, v in AMG_BY_GAUGE[args.gauge].items():
         if getattr(args, k) is None:
@@ -852,7 +867,8 @@ def main():
     log(f"case {case.name}: {case.n_vert} vertices, {case.n_elem} tets, generated in {t_gen:.1f} s")
     t0 = time.perf_counter()
     amg_kw = amg_flags(args)
-    solver = KnpSolver(case, solve=solve_opts(rtol=1e-6, restart=args.restart, max_it=2000), gauge=args.gauge)
+    solver = KnpSolver(case, solve=solve_opts(rtol=1e-6, restart=args.restart, max_it=2000), gauge=args.gauge,
+                       extrapolate=args.initial_guess == "extrap")
     torch.cuda.synchronize()
     t_upload = time.perf_counter() - t0
     info = solver.info
@@ -925,7 +941,7 @@ def main():
         "config": {"workload": f"4x4x4 lattice of jittered box cells, {case.shape[0]}^3 grid x 6 tets, "
                                f"N={info.N} unknowns, 16 HH + 48 {'leak' if args.passive == 'leak' else 'Kir-Na/K'} cells, dt=0.05 ms, FGMRES({args.restart}) rtol 1e-6",
                    "N": info.N, "nnz_A": info.nnz_A, "nnz_P0": info.nnz_P0, "parallelism": "1 GPU",
-                   "gauge": args.gauge, "amg": amg_kw},
+                   "gauge": args.gauge, "initial_guess": args.initial_guess, "amg": amg_kw},
         "its_per_step": {k: float(sum(r["its"]) / len(r["its"])) for k, r in runs.items()},
         "steps_per_s": {k: round(r["steps_per_s"], 3) for k, r in runs.items()},
         "ms_per_step_by_precision": {k: round(r["ms_per_step"], 2) for k, r in runs.items()},

@@ -293,6 +293,13 @@ knp_status knp_adjoint_solve(knp_ctx *ctx, const double *rhs, double *lambda,
 knp_status knp_step_vjp(knp_ctx *ctx, const double *u_prev, const double *u_n,
                         const double *lambda_n, double *u_prev_bar, double *theta_bar);
 
+/* Initial guess for the next step's solve from the last two steps' solutions:
+ * x0 = 2 u1 - u2 (device [N] each; u1 = u_{n-1}, u2 = u_{n-2}; x0 may alias either).
+ * The paper starts each solve from the previous step (Sec. "Solver configurations");
+ * the linear extrapolation in time is an alternative start that the caller may pass to
+ * knp_gmres_solve as x.  Needs an uploaded mesh (N); blocks until done. */
+knp_status knp_extrapolate(knp_ctx *ctx, const double *u1, const double *u2, double *x0);
+
 /* Operator hooks for tests and measurement (device vectors of length N):
  *   which 0: y = S A S x (the stored system matrix)
  *   which 1: y = one V-cycle on S P_0 S applied to x

@@ -1008,6 +1008,19 @@ knp_status knp_get_scaling(knp_ctx *c, double *s) {
     });
 }
 
+knp_status knp_extrapolate(knp_ctx *c, const double *u1, const double *u2, double *x0) {
+    return guarded(c, [&]() -> knp_status {
+        need_device(c);
+        if (!c->have_mesh) return fail(c, KNP_E_STATE, "no mesh");
+        if (!u1 || !u2 || !x0) return fail(c, KNP_E_ARG, "NULL vector");
+        hip_check(hipSetDevice(c->device), "set device");
+        launch::lincomb(c->hm.N, 2.0, u1, -1.0, u2, x0, c->stream);
+        hip_check(hipGetLastError(), "extrapolate launch");
+        hip_check(hipStreamSynchronize(c->stream), "sync");
+        return KNP_OK;
+    });
+}
+
 knp_status knp_get_values(knp_ctx *c, double *vals) {
     return guarded(c, [&]() -> knp_status {
         need_device(c);

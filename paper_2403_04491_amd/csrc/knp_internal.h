@@ -539,6 +539,8 @@ void scale_by_inv_norm(int64_t n, const double *w, const double *nrm2, double *v
 void add_scaled(int64_t n, double a, const double *x, double *y, hipStream_t s);   // y += a x
 void axpby(int64_t n, double a, const double *x, double b, double *y, hipStream_t s);
 void sub(int64_t n, const double *a, const double *b, double *y, hipStream_t s);   // y = a - b
+void lincomb(int64_t n, double a, const double *x, double b, const double *y, double *out,
+             hipStream_t s);   // out = a x + b y
 int reduce_blocks(int64_t n);
 
 // the constant-potential gauge inside the solver (nullspace.hip)

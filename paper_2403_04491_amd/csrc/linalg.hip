@@ -580,6 +580,12 @@ __global__ void k_axpby(int64_t n, double a, const double *x, double b, double *
         y[i] = a * x[i] + (b == 0.0 ? 0.0 : b * y[i]);
 }
 
+// out = a x + b y; operands may alias the output (element-wise)
+__global__ void k_lincomb(int64_t n, double a, const double *x, double b, const double *y, double *out) {
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+        out[i] = a * x[i] + b * y[i];
+}
+
 // operands may alias the output (element-wise)
 __global__ void k_sub(int64_t n, const double *a, const double *b, double *y) {
     for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
@@ -739,6 +745,10 @@ void add_scaled(int64_t n, double a, const double *x, double *y, hipStream_t s) 
 
 void axpby(int64_t n, double a, const double *x, double b, double *y, hipStream_t s) {
     hipLaunchKernelGGL(k_axpby, dim3(stream_grid(n)), dim3(TPB), 0, s, n, a, x, b, y);
+}
+
+void lincomb(int64_t n, double a, const double *x, double b, const double *y, double *out, hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(k_lincomb, dim3(stream_grid(n)), dim3(TPB), 0, s, n, a, x, b, y, out);
 }
 
 void sub(int64_t n, const double *a, const double *b, double *y, hipStream_t s) {

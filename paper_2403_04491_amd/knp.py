@@ -23,7 +23,7 @@ EXPORTS = ["knp_create", "knp_destroy", "knp_last_error", "knp_mesh_upload", "kn
            "knp_mesh_upload_p2", "knp_get_edges",
            "knp_gmres_solve", "knp_adjoint_solve", "knp_step_vjp", "knp_apply",
            "knp_get_scaling", "knp_get_values", "knp_timing", "knp_timing_read", "knp_amg_stats",
-           "knp_set_gauge"]
+           "knp_set_gauge", "knp_extrapolate"]
 TIMERS = ["spmv_A", "cheb_L0", "resid_L0", "vcycle", "assembly", "resid_A"]
 
 
@@ -99,6 +99,7 @@ def load_library(path: str = _LIB_PATH) -> C.CDLL:
     lib.knp_assemble_step_noalloc.argtypes = [P, D, D, P, P, P, P]
     lib.knp_amg_setup.argtypes = [P, C.POINTER(AmgOpts)]
     lib.knp_set_gauge.argtypes = [P, C.c_int32]
+    lib.knp_extrapolate.argtypes = [P, P, P, P]
     lib.knp_gmres_solve.argtypes = [P, P, P, C.POINTER(SolveOpts), C.POINTER(SolveInfo)]
     lib.knp_adjoint_solve.argtypes = [P, P, P, C.POINTER(SolveOpts), C.POINTER(SolveInfo)]
     lib.knp_step_vjp.argtypes = [P, P, P, P, P, P]
@@ -268,6 +269,13 @@ class Context:
         """knp_set_gauge: 0 = point condition on the reference phi_e DOF in the system;
         1 = system without it, nullspace handled by the forward solve."""
         self._check(self._lib.knp_set_gauge(self._c, int(mode)))
+
+    def extrapolate(self, u1, u2, x0):
+        """knp_extrapolate: x0 = 2 u1 - u2 (device float64 [N])."""
+        import torch
+        N = self.info.N
+        self._check(self._lib.knp_extrapolate(self._c, _dptr(u1, torch.float64, N), _dptr(u2, torch.float64, N),
+                                              _dptr(x0, torch.float64, N)))
 
     def amg_setup(self, opts: AmgOpts | None = None):
         self._check(self._lib.knp_amg_setup(self._c, C.byref(opts) if opts is not None else None))

@@ -39,13 +39,16 @@ AMG_BY_GAUGE = {
 class KnpSolver:
     """Holds one context and the state (u, gates) of a run on one GPU."""
 
-    def __init__(self, case, device=0, amg=None, solve=None, theta=None, order=1, gauge=0):
+    def __init__(self, case, device=0, amg=None, solve=None, theta=None, order=1, gauge=0, extrapolate=False):
         """case: a vertex mesh with per-vertex data; order 2 adds the edge nodes (P2);
         gauge: 0 = point condition on phi_e in the system, 1 = nullspace handled by the
-        solve (knp_set_gauge)."""
+        solve (knp_set_gauge); extrapolate: start each solve from 2 u_{n-1} - u_{n-2}
+        (knp_extrapolate) once two steps are known, instead of from u_{n-1}."""
         self.case = case
         self.order = order
         self.gauge = gauge
+        self.extrapolate = extrapolate
+        self._u_prev = None
         self.dev = torch.device("cuda", device)
         self.ctx = Context(device)
         self.info = self.ctx.mesh_upload(case.dim, case.xyz, case.elem, case.tag, case.pin_vertex, order=order)
@@ -67,6 +70,16 @@ class KnpSolver:
         self.amg_ready = False
         self.n = 0
         self.history = []
+
+    @property
+    def u(self):
+        return self._u
+
+    @u.setter
+    def u(self, v):
+        # a state set from outside starts a new history (no extrapolation from it)
+        self._u = v
+        self._u_prev = None
 
     def membrane_rows(self):
         """Device indices (phi_i rows, phi_e rows) of the membrane nodes (vertices, and
@@ -93,7 +106,11 @@ class KnpSolver:
             self.amg_ready = True
 
     def solve(self, allow_noconv=False, opts=None):
-        x = self.u.clone()
+        if self.extrapolate and self._u_prev is not None:
+            x = torch.empty_like(self._u)
+            self.ctx.extrapolate(self._u, self._u_prev, x)
+        else:
+            x = self._u.clone()
         info, ok = self.ctx.gmres_solve(self.f, x, opts if opts is not None else self.solve_opts,
                                         allow_noconv=allow_noconv)
         return x, info, ok
@@ -101,7 +118,7 @@ class KnpSolver:
     def step(self, allow_noconv=False, opts=None):
         self.assemble()
         x, info, ok = self.solve(allow_noconv, opts)
-        self.u = x
+        self._u_prev, self._u = self._u, x
         self.n += 1
         self.history.append({"n": self.n, "its": info.its, "rel_res": info.rel_res, "converged": ok})
         return info

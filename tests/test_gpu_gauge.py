@@ -174,3 +174,26 @@ def test_gauge_call_errors():
     with pytest.raises(knp.KnpError) as ei:
         s2.ctx.set_gauge(2)
     assert ei.value.status == 1
+
+
+def test_extrapolated_start_reaches_the_oracle_steps():
+    """knp_extrapolate gives 2 u1 - u2 bit for bit (2 u1 is exact, so one rounding either
+    way), and solves started from it (gauge 1, from the third step on) meet the oracle's
+    steps at the parity setting within 1e-8 per block, element-wise."""
+    case = config_case(3, per_pitch=4)
+    n_steps = 4
+    print(f"[extrapolated start] {case.name} steps={n_steps}", flush=True)
+    ref = timeloop.run(case, n_steps=n_steps)["u"]
+    s = KnpSolver(case, gauge=1, extrapolate=True, amg=amg_opts(precision=0), solve=solve_opts(**PARITY))
+    rng = np.random.default_rng(5)
+    u1, u2 = T(rng.standard_normal(s.info.N)), T(rng.standard_normal(s.info.N))
+    x0 = torch.empty_like(u1)
+    s.ctx.extrapolate(u1, u2, x0)
+    assert torch.equal(x0, 2.0 * u1 - u2)
+    for n in range(1, n_steps + 1):
+        info = s.step()
+        e = errs(s.info, s.u.cpu().numpy(), ref[n])
+        print(f"  step {n}: its {info.its} " + " ".join(f"{k} {a:.1e}/{b:.1e}" for k, (a, b) in e.items()),
+              flush=True)
+        for k, (a, b) in e.items():
+            assert a <= 1e-8 and b <= 1e-8, (n, k, a, b)
