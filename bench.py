@@ -770,7 +770,8 @@ def main():
                     help="start of each step's solve: u_{n-1} (the paper's) or 2 u_{n-1} - u_{n-2} "
                          "(knp_extrapolate) once two steps are known; default extrap, except prev "
                          "for --config2, whose 3D action potential the extrapolation overshoots "
-                         "(up to 500 iterations in a step)")
+                         "(up to 500 iterations in a step), and for --large, whose timed steps "
+                         "follow the noisy first step (12 instead of 4 iterations in step 3)")
     ap.add_argument("--gauge", type=int, default=1, choices=[0, 1],
                     help="0: point condition on phi_e in the system; 1: system without it, the "
                          "constant-potential nullspace handled by the solve (knp_set_gauge)")
@@ -827,7 +828,7 @@ def main():
     ap.add_argument("--fd-rtol-adj", type=float, default=1e-8)
     args = ap.parse_args()
     if args.initial_guess is None:
-        args.initial_guess = "prev" if args.config2 else "extrap"
+        args.initial_guess = "prev" if (args.config2 or args.large) else "extrap"
     if args.adjoint:
         args.gauge = 0   # the adjoint solve and the VJPs need the point condition
     from paper_2403_04491_amd.simulate import AMG_BY_GAUGE   # 93 against 58 steps/s (gauge 1)
