@@ -19,6 +19,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 from knp_inputs import config_case, model_a_case  # noqa: E402
+from knp_inputs.fan import fan_case  # noqa: E402
 from oracle import timeloop  # noqa: E402
 from oracle.assemble import Assembler, initial_gates, initial_state  # noqa: E402
 from oracle.timeloop import advance_gates  # noqa: E402
@@ -97,6 +98,9 @@ STEP_CASES = {
     "cfg1": (lambda: config_case(1), 4),
     "modelA3d_nx8_hh": (lambda: model_a_case(3, 8, "hh", 5e-5, 2, cfg_id=2), 3),
     "lattice4_pp4": (lambda: config_case(3, per_pitch=4), 2),
+    "lattice4_pp4_kir": (lambda: config_case(3, per_pitch=4, passive="kir"), 2),
+    # a vertex of degree 41: the product-form assembly path of order-1 meshes
+    "fan_hh": (lambda: fan_case(membrane="hh", n_steps=2), 2),
 }
 
 

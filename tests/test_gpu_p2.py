@@ -83,17 +83,19 @@ def test_p2_assembly_matches_oracle(name):
             assert np.allclose(s.gates.cpu().numpy()[hh], w_ref[hh], rtol=1e-13, atol=1e-15)
 
 
-@pytest.mark.parametrize("name,precision,tol", [
-    ("modelA2d_nx8_hh", 0, 1e-8), ("modelA3d_nx4_hh", 0, 1e-8), ("modelA2d_nx16_leak", 0, 1e-8),
-    ("modelA2d_nx8_hh", 1, 1e-6),
+@pytest.mark.parametrize("name,precision,tol,gauge", [
+    ("modelA2d_nx8_hh", 0, 1e-8, 0), ("modelA3d_nx4_hh", 0, 1e-8, 0), ("modelA2d_nx16_leak", 0, 1e-8, 0),
+    ("modelA2d_nx8_hh", 1, 1e-6, 0),
+    # the system without the point condition (knp_set_gauge 1) reaches the same steps
+    ("modelA2d_nx8_hh", 0, 1e-8, 1), ("modelA3d_nx4_hh", 1, 1e-6, 1),
 ])
-def test_p2_time_steps_match_oracle(name, precision, tol):
+def test_p2_time_steps_match_oracle(name, precision, tol, gauge):
     base = CASES[name]()
     case = p2_case(base)
     steps = base.n_steps
-    print(f"[P2 steps] {name} steps={steps} precision={precision}", flush=True)
+    print(f"[P2 steps] {name} steps={steps} precision={precision} gauge={gauge}", flush=True)
     ref = timeloop.run(case, n_steps=steps)["u"]
-    s = KnpSolver(base, order=2, amg=amg_opts(precision=precision), solve=solve_opts(**PARITY))
+    s = KnpSolver(base, order=2, gauge=gauge, amg=amg_opts(precision=precision), solve=solve_opts(**PARITY))
     its = []
     for n in range(1, steps + 1):
         info = s.step()
