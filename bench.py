@@ -298,7 +298,7 @@ def amg_flags(args):
                 coarse_drop=args.coarse_drop, cheb_pre_degree=args.cheb_pre_degree,
                 coarse_pre_degree=args.coarse_pre_degree, coarse_post_degree=args.coarse_post_degree,
                 coarse_max=args.coarse_max, field_split=args.field_split,
-                shared_ion_aggregates=args.shared_ion_aggregates)
+                shared_ion_aggregates=args.shared_ion_aggregates, coarse_graph=args.coarse_graph)
 
 
 def model_a_bench(args, log):
@@ -785,6 +785,10 @@ def main():
     ap.add_argument("--coarse-pre-degree", type=int, default=0)
     ap.add_argument("--coarse-post-degree", type=int, default=None, help="default: tuned per gauge")
     ap.add_argument("--coarse-max", type=int, default=2000)
+    ap.add_argument("--coarse-graph", type=int, default=0, choices=[0, 1],
+                    help="1: the AMG levels below the finest replayed as one HIP graph; 0: launched one "
+                         "by one (measured the same speed: the small kernels' own duration, not their "
+                         "launch, sets the time)")
     ap.add_argument("--shared-ion-aggregates", type=int, default=0, choices=[0, 1],
                     help="1: the finest level's Na and Cl blocks reuse the K block's aggregates")
     ap.add_argument("--field-split", type=int, default=0, choices=[0, 1],

@@ -112,6 +112,11 @@ typedef struct {
     int32_t shared_ion_aggregates;  /* 1: the Na+ and Cl- blocks of the finest level
                                reuse the aggregates of the K+ block (one aggregation
                                for the three ion blocks); 0: each block its own   */
+    int32_t coarse_graph;   /* 1: the levels below the finest run as one HIP graph,
+                               captured at the first V-cycle after the setup and
+                               replayed (the same kernels on the same buffers, so the
+                               same results bit for bit, with one launch call);
+                               0: their kernels are launched one by one          */
 } knp_amg_opts;
 
 typedef struct {
@@ -257,7 +262,7 @@ knp_status knp_set_gauge(knp_ctx *ctx, int32_t mode);
  * Chebyshev smoothing on [lmax/2.5, lmax] of degree 0 before and 5 after the coarse
  * correction on the finest level and 0 and 1 on the coarser levels, coarse_max
  * 2000, max_levels 20, coarse_drop 0.01, operator_step 0, field_split 0,
- * shared_ion_aggregates 0). */
+ * shared_ion_aggregates 0, coarse_graph 0). */
 knp_status knp_amg_setup(knp_ctx *ctx, const knp_amg_opts *opts);
 
 /* Shape of the hierarchy built by knp_amg_setup: number of levels (<= 32) and,

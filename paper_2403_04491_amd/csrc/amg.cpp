@@ -369,9 +369,16 @@ void DevCsr::upload(const Csr &h, bool fp32, hipStream_t s) {
     hip_check(hipStreamSynchronize(s), "upload");
 }
 
-Amg::~Amg() { clear(); }
+Amg::~Amg() {
+    clear();
+    if (capture_stream) (void)hipStreamDestroy(capture_stream);
+    capture_stream = nullptr;
+}
 
 void Amg::clear() {
+    if (coarse_exec) (void)hipGraphExecDestroy(coarse_exec);
+    coarse_exec = nullptr;
+    coarse_out = nullptr;
     for (Level *l : levels) delete l;
     levels.clear();
     ready = false;
@@ -450,6 +457,7 @@ void amg_build(Amg &amg, const HostMesh &m, const std::vector<double> &p0_vals, 
     amg.coarse_post = std::max(1, o.coarse_post_degree);
     amg.ratio = o.cheb_ratio;
     amg.field_split = o.field_split == 1;
+    amg.coarse_graph = o.coarse_graph == 1;
     // P_0 in CSR, in the solver's order (DOF off_r + 4 j + f): per region the scalar
     // pattern of the region for each field.  p0_vals and near_null come in ABI order
     // (block by block: region r, field f, then the pattern row by row).
@@ -896,10 +904,44 @@ struct LV<float> {
     static const float *R(Level *L) { return L->R.val32.p; }
 };
 
+template <typename T>
+T *vcycle_level(Amg &amg, size_t l, const T *b, hipStream_t s, Timers *tm, T *out = nullptr);
+
+// The levels below the finest, from level 1's right-hand side bc (a level-1 buffer):
+// launched one by one, or as the HIP graph of those launches (captured on the first call
+// after a setup).  No timer event is recorded below the finest level, and these levels
+// issue kernels only, so the capture holds the same work.
+template <typename T>
+T *coarse_cycle(Amg &amg, const T *bc, hipStream_t s, Timers *tm) {
+    if (!amg.coarse_graph) return vcycle_level<T>(amg, 1, bc, s, tm);
+    if (!amg.coarse_exec) {
+        if (!amg.capture_stream)
+            hip_check(hipStreamCreateWithFlags(&amg.capture_stream, hipStreamNonBlocking), "capture stream");
+        hipStream_t cs = amg.capture_stream;
+        hip_check(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "begin capture");
+        T *xc = nullptr;
+        hipGraph_t g = nullptr;
+        try {
+            xc = vcycle_level<T>(amg, 1, bc, cs, nullptr);
+        } catch (...) {
+            (void)hipStreamEndCapture(cs, &g);
+            if (g) (void)hipGraphDestroy(g);
+            throw;
+        }
+        hip_check(hipStreamEndCapture(cs, &g), "end capture");
+        const hipError_t e = hipGraphInstantiate(&amg.coarse_exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        hip_check(e, "instantiate the coarse-level graph");
+        amg.coarse_out = xc;
+    }
+    hip_check(hipGraphLaunch(amg.coarse_exec, s), "coarse-level graph");
+    return static_cast<T *>(amg.coarse_out);
+}
+
 // V-cycle on level l: solves approximately A_l x = b, with b and the result in
 // the level's own buffers; returns the buffer holding x.
 template <typename T>
-T *vcycle_level(Amg &amg, size_t l, const T *b, hipStream_t s, Timers *tm, T *out = nullptr) {
+T *vcycle_level(Amg &amg, size_t l, const T *b, hipStream_t s, Timers *tm, T *out) {
     Level *L = amg.levels[l];
     if (l + 1 == amg.levels.size()) {
         T *x = LV<T>::x(L);
@@ -996,7 +1038,7 @@ T *vcycle_level(Amg &amg, size_t l, const T *b, hipStream_t s, Timers *tm, T *ou
             launch::spmv<T, T, T>(L->R.view(), LV<T>::R(L), b, bc, s);
         }
     }
-    T *xc = vcycle_level<T>(amg, l + 1, bc, s, tm);
+    T *xc = l == 0 ? coarse_cycle<T>(amg, bc, s, tm) : vcycle_level<T>(amg, l + 1, bc, s, tm);
     if (dpre > 0) {
         launch::prolong_add<T>(L->P.view(), LV<T>::P(L), xc, cur, s);
     } else {

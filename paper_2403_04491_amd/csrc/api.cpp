@@ -902,14 +902,15 @@ knp_status knp_amg_setup(knp_ctx *c, const knp_amg_opts *opts) {
     return guarded(c, [&]() -> knp_status {
         need_device(c);
         if (!c->assembled) return fail(c, KNP_E_STATE, "knp_assemble_step must come first");
-        knp_amg_opts o{0, 0.6, 5, 2.5, 2000, 20, 0.01, 0, 0, 1, 0, 0, 0};
+        knp_amg_opts o{0, 0.6, 5, 2.5, 2000, 20, 0.01, 0, 0, 1, 0, 0, 0, 0};
         if (opts) o = *opts;
         if (o.precision != 0 && o.precision != 1) return fail(c, KNP_E_ARG, "precision must be 0 or 1");
         if (!(o.strength > 0.0 && o.strength < 1.0) || o.cheb_degree < 1 || !(o.cheb_ratio > 1.0) ||
             o.coarse_max < 1 || o.max_levels < 1 || !(o.coarse_drop >= 0.0 && o.coarse_drop < 1.0) ||
             o.cheb_pre_degree < 0 || o.coarse_pre_degree < 0 || o.coarse_post_degree < 1 ||
             (o.operator_step != 0 && o.operator_step != 1) || (o.field_split != 0 && o.field_split != 1) ||
-            (o.shared_ion_aggregates != 0 && o.shared_ion_aggregates != 1))
+            (o.shared_ion_aggregates != 0 && o.shared_ion_aggregates != 1) ||
+            (o.coarse_graph != 0 && o.coarse_graph != 1))
             return fail(c, KNP_E_ARG, "invalid AMG options");
         hip_check(hipSetDevice(c->device), "set device");
         if (o.operator_step == 1)

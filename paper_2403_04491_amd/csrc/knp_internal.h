@@ -371,6 +371,14 @@ struct Amg {
     int64_t n_blocks = 0;
     std::vector<int64_t> level_nnz, level_n;
     double vcycle_bytes = 0.0;       // algorithmic bytes of one V-cycle (its timer class)
+    // the levels below the finest as one HIP graph: captured (on a stream of its own; the
+    // caller's may be the legacy default stream, which cannot be captured) at the first
+    // V-cycle after a setup, replayed on the caller's stream; the levels' buffers are fixed,
+    // so every replay runs the same kernels on the same data as the launches would
+    bool coarse_graph = false;
+    hipStream_t capture_stream = nullptr;
+    hipGraphExec_t coarse_exec = nullptr;
+    void *coarse_out = nullptr;      // the level-1 buffer the sub-cycle leaves its result in
     ~Amg();
     void clear();
 };

@@ -56,7 +56,7 @@ class AmgOpts(C.Structure):
                 ("coarse_drop", C.c_double), ("cheb_pre_degree", C.c_int32),
                 ("coarse_pre_degree", C.c_int32), ("coarse_post_degree", C.c_int32),
                 ("operator_step", C.c_int32), ("field_split", C.c_int32),
-                ("shared_ion_aggregates", C.c_int32)]
+                ("shared_ion_aggregates", C.c_int32), ("coarse_graph", C.c_int32)]
 
 
 class SolveOpts(C.Structure):
@@ -146,10 +146,10 @@ def _hptr(a):
 
 def amg_opts(precision=0, strength=0.6, cheb_degree=5, cheb_ratio=2.5, coarse_max=2000, max_levels=20,
              coarse_drop=0.01, cheb_pre_degree=0, coarse_pre_degree=0, coarse_post_degree=1, operator_step=0,
-             field_split=0, shared_ion_aggregates=0):
+             field_split=0, shared_ion_aggregates=0, coarse_graph=0):
     return AmgOpts(precision, strength, cheb_degree, cheb_ratio, coarse_max, max_levels, coarse_drop,
                    cheb_pre_degree, coarse_pre_degree, coarse_post_degree, operator_step, field_split,
-                   shared_ion_aggregates)
+                   shared_ion_aggregates, coarse_graph)
 
 
 def solve_opts(rtol=1e-6, restart=30, max_it=2000, reorth=0, precond=1):
