@@ -250,8 +250,9 @@ knp_status knp_assemble_step_noalloc(knp_ctx *ctx, double t_n, double dt, const 
  *     approximation of the same solution as in mode 0; S and P_0 are formed the same
  *     way.  knp_get_values and knp_apply(0/2) show the system without the condition;
  *     knp_adjoint_solve and knp_step_vjp need mode 0 (KNP_E_STATE).
- * KNP_E_ARG for another mode, or for mode 1 on a mesh whose cells' intracellular
- * nodes or membrane nodes neighbour those of another cell. */
+ * KNP_E_ARG for another mode.  Mode 1 needs the cells' intracellular DOFs not to
+ * couple, which knp_mesh_upload already ensures (it refuses cells that share a vertex);
+ * the call checks it again and returns KNP_E_ARG if it fails. */
 knp_status knp_set_gauge(knp_ctx *ctx, int32_t mode);
 
 /* Build the algebraic-multigrid hierarchy of P_0 (eq. ``P_prec``), frozen for all

@@ -201,3 +201,27 @@ def test_extrapolated_start_reaches_the_oracle_steps():
               flush=True)
         for k, (a, b) in e.items():
             assert a <= 1e-8 and b <= 1e-8, (n, k, a, b)
+
+
+def test_gauge1_noalloc_assembly_matches_the_allocating_one():
+    """knp_assemble_step_noalloc assembles the system without the point condition too:
+    values, f and gates bit for bit equal to knp_assemble_step's in gauge 1."""
+    case = config_case(3, per_pitch=4)
+    s = KnpSolver(case, gauge=1)
+    s.assemble(1)
+    gen = torch.Generator(device=s.dev).manual_seed(3)
+    u_prev = s.u * (1.0 + 1e-3 * (torch.rand(s.info.N, dtype=torch.float64, device=s.dev, generator=gen) - 0.5))
+    out = []
+    for fn in (s.ctx.assemble_step, s.ctx.assemble_step_noalloc):
+        g = s.gates.clone()
+        f = torch.empty(s.info.N, dtype=torch.float64, device=s.dev)
+        fn(2 * case.dt, case.dt, u_prev, g, s.theta, f)
+        vals = torch.empty(s.info.nnz_A, dtype=torch.float64, device=s.dev)
+        s.ctx.get_values(vals)
+        torch.cuda.synchronize()
+        out.append((vals.cpu().numpy(), f.cpu().numpy(), g.cpu().numpy()))
+    for a, b in zip(*out):
+        assert np.array_equal(a, b)
+    p = s.info.pin_dof
+    vals = out[0][0]
+    assert np.count_nonzero(vals[s.rowptr[p]:s.rowptr[p + 1]]) > 1   # the reference row is whole
