@@ -101,6 +101,7 @@ template struct DArray<int32_t>;
 template struct DArray<int64_t>;
 template struct DArray<uint32_t>;
 template struct DArray<uint8_t>;
+template struct DArray<uint16_t>;
 template struct DArray<RowGroup>;
 
 }  // namespace knp

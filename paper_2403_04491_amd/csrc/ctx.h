@@ -119,8 +119,9 @@ struct knp_ctx {
     bool ns_basis = false, ns_stale = true;
     int64_t ns_nrows = 0;   // storage rows of membrane nodes (the rows W is computed on)
     knp::DArray<int32_t> d_ns_owner, d_ns_idx, d_ns_rows;
-    knp::DArray<int64_t> d_ns_ptr;
-    knp::DArray<double> d_ns_zs, d_ns_u, d_ns_w, d_ns_e, d_ns_sum;
+    knp::DArray<int64_t> d_ns_ptr, d_ns_wptr;   // cells' DOF lists; each membrane row's list below
+    knp::DArray<uint16_t> d_ns_woff;            // in-row positions of its intracellular potential columns
+    knp::DArray<double> d_ns_zs, d_ns_u, d_ns_w, d_ns_e, d_ns_sum, d_ns_part;
 
     // preconditioner
     std::vector<double> p0_vals, near_null;
@@ -223,6 +224,8 @@ knp_status krylov_solve(knp_ctx *c, bool transpose, const double *b, double *x, 
 void ensure_transpose(knp_ctx *c);
 // y = (S A S) x or its transpose, FP64; timed under `timer` (a KNP_TIMER_* class)
 void apply_operator(knp_ctx *c, bool transpose, const double *x, double *y, int timer = KNP_TIMER_SPMV_A);
+// y = b - (S A S) x (or the transpose), FP64, timed as KNP_TIMER_RESID_A
+void residual(knp_ctx *c, bool transpose, const double *x, const double *b, double *y);
 // gauge 1: the cell ownership of every storage DOF and the per-cell lists of the
 // intracellular potential DOFs (host work and upload; needs the mesh)
 void gauge_build(knp_ctx *c);

@@ -552,18 +552,21 @@ void lincomb(int64_t n, double a, const double *x, double b, const double *y, do
 int reduce_blocks(int64_t n);
 
 // the constant-potential gauge inside the solver (nullspace.hip)
-// out[k] = sum_{q in [ptr[k], ptr[k+1])} zs[q] v[idx[q]], one workgroup per cell
-void cell_dot(int ncell, const int64_t *ptr, const int32_t *idx, const double *zs, const double *v, double *out,
-              hipStream_t s);
+// out[k] = sum_{q in [ptr[k], ptr[k+1])} zs[q] v[idx[q]]: CELL_SPLIT workgroups per cell
+// write part[k * CELL_SPLIT + c], then the partials are added in order
+constexpr int CELL_SPLIT = 8;
+void cell_dot(int ncell, const int64_t *ptr, const int32_t *idx, const double *zs, const double *v, double *part,
+              double *out, hipStream_t s);
 // zs[q] = 1 / sc[int2ext[idx[q]]]; u = 0 except u[idx[q]] = zs[q]
 void cell_basis(int64_t n, int64_t nidx, const int32_t *idx, const int32_t *int2ext, const double *sc, double *zs,
                 double *u, hipStream_t s);
 // c_k = sum[k] / E[k]; r[i] -= c_owner(i) W[i], y[i] += c_owner(i) u[i] where owner(i) >= 0
 void cell_correct(int64_t n, const int32_t *owner, const double *W, const double *u, const double *sum,
                   const double *E, double *r, double *y, hipStream_t s);
-// y[rows[t]] = (A x)[rows[t]] for the listed storage rows (CSR storage view), others untouched
-void rows_spmv(int64_t n, const int32_t *rows, const int64_t *rowptr, const int32_t *col, const double *val,
-               const double *x, double *y, hipStream_t s);
+// y[rows[t]] = sum of val[q] x[col[q]] over the listed entries q = rowptr[rows[t]] + off[e],
+// e in [wptr[t], wptr[t+1]) (CSR storage view); other rows untouched
+void rows_sub_spmv(int64_t n, const int32_t *rows, const int64_t *wptr, const uint16_t *off, const int64_t *rowptr,
+                   const int32_t *col, const double *val, const double *x, double *y, hipStream_t s);
 void fill_zero(int64_t n, double *y, hipStream_t s);
 // x[j] -= *ref on [a0, a1) and [b0, b1)
 void shift_potentials(int64_t a0, int64_t a1, int64_t b0, int64_t b1, const double *ref, double *x, hipStream_t s);

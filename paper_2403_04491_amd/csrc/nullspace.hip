@@ -29,13 +29,16 @@ namespace {
 
 constexpr int TPB = 256;
 
-// out[k] = sum over q in [ptr[k], ptr[k+1]) of zs[q] * v[idx[q]]
-__global__ void __launch_bounds__(TPB) k_cell_dot(const int64_t *__restrict__ ptr, const int32_t *__restrict__ idx,
-                                                  const double *__restrict__ zs, const double *__restrict__ v,
-                                                  double *__restrict__ out) {
+// part[k * CELL_SPLIT + c] = sum over chunk c of [ptr[k], ptr[k+1]) of zs[q] * v[idx[q]]
+// (CELL_SPLIT workgroups per cell, each a fixed-order tree over its chunk)
+__global__ void __launch_bounds__(TPB) k_cell_dot_part(const int64_t *__restrict__ ptr, const int32_t *__restrict__ idx,
+                                                       const double *__restrict__ zs, const double *__restrict__ v,
+                                                       double *__restrict__ part) {
     __shared__ double red[TPB];
-    const int k = int(blockIdx.x);
-    const int64_t a = ptr[k], b = ptr[k + 1];
+    const int k = int(blockIdx.x) / CELL_SPLIT, c = int(blockIdx.x) % CELL_SPLIT;
+    const int64_t a0 = ptr[k], b0 = ptr[k + 1];
+    const int64_t chunk = (b0 - a0 + CELL_SPLIT - 1) / CELL_SPLIT;
+    const int64_t a = a0 + c * chunk, b = a + chunk < b0 ? a + chunk : b0;
     double s = 0.0;
     for (int64_t q = a + int64_t(threadIdx.x); q < b; q += TPB) s += zs[q] * v[idx[q]];
     red[threadIdx.x] = s;
@@ -45,7 +48,17 @@ __global__ void __launch_bounds__(TPB) k_cell_dot(const int64_t *__restrict__ pt
         if (int(threadIdx.x) < h) red[threadIdx.x] += red[threadIdx.x + h];
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[k] = red[0];
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// out[k] = the cell's CELL_SPLIT partial sums added in order
+__global__ void k_cell_dot_sum(int ncell, const double *__restrict__ part, double *__restrict__ out) {
+    const int k = int(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= ncell) return;
+    double s = 0.0;
+#pragma unroll
+    for (int c = 0; c < CELL_SPLIT; ++c) s += part[k * CELL_SPLIT + c];
+    out[k] = s;
 }
 
 // zs[q] = 1 / S of storage DOF idx[q] (S in ABI order), and u[idx[q]] = zs[q]
@@ -91,24 +104,31 @@ __global__ void k_shift(int64_t a0, int64_t a1, int64_t b0, int64_t b1, const do
     }
 }
 
-// y[rows[t]] = the row's stored entries times x; 16 lanes per listed row (rows hold a
-// few dozen entries), fixed order: lane-strided partial sums, then a butterfly
+// y[rows[t]] = the listed entries of row rows[t] times x: the entries at storage positions
+// rowptr[rows[t]] + off[e] for e in [wptr[t], wptr[t+1]); 16 lanes per listed row, fixed
+// order (lane-strided partial sums, then a butterfly)
 constexpr int RL = 16;
-__global__ void __launch_bounds__(TPB) k_rows_spmv(int64_t n, const int32_t *__restrict__ rows,
-                                                   const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col,
-                                                   const double *__restrict__ val, const double *__restrict__ x,
-                                                   double *__restrict__ y) {
+__global__ void __launch_bounds__(TPB) k_rows_sub_spmv(int64_t n, const int32_t *__restrict__ rows,
+                                                       const int64_t *__restrict__ wptr,
+                                                       const uint16_t *__restrict__ off,
+                                                       const int64_t *__restrict__ rowptr,
+                                                       const int32_t *__restrict__ col,
+                                                       const double *__restrict__ val, const double *__restrict__ x,
+                                                       double *__restrict__ y) {
     const int64_t t = (int64_t(blockIdx.x) * TPB + threadIdx.x) / RL;
     const int lane = int(threadIdx.x % RL);
     double s = 0.0;
     int32_t r = -1;
     if (t < n) {
         r = rows[t];
-        const int64_t a = rowptr[r], b = rowptr[r + 1];
-        for (int64_t q = a + lane; q < b; q += RL) s += val[q] * x[col[q]];
+        const int64_t base = rowptr[r];
+        for (int64_t e = wptr[t] + lane; e < wptr[t + 1]; e += RL) {
+            const int64_t q = base + off[e];
+            s += val[q] * x[col[q]];
+        }
     }
 #pragma unroll
-    for (int off = RL / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, RL);
+    for (int o = RL / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, RL);
     if (lane == 0 && r >= 0) y[r] = s;
 }
 
@@ -121,10 +141,11 @@ inline unsigned grid(int64_t n) {
 
 }  // namespace
 
-void cell_dot(int ncell, const int64_t *ptr, const int32_t *idx, const double *zs, const double *v, double *out,
-              hipStream_t s) {
+void cell_dot(int ncell, const int64_t *ptr, const int32_t *idx, const double *zs, const double *v, double *part,
+              double *out, hipStream_t s) {
     if (ncell <= 0) return;
-    hipLaunchKernelGGL(k_cell_dot, dim3(unsigned(ncell)), dim3(TPB), 0, s, ptr, idx, zs, v, out);
+    hipLaunchKernelGGL(k_cell_dot_part, dim3(unsigned(ncell * CELL_SPLIT)), dim3(TPB), 0, s, ptr, idx, zs, v, part);
+    hipLaunchKernelGGL(k_cell_dot_sum, dim3(unsigned((ncell + TPB - 1) / TPB)), dim3(TPB), 0, s, ncell, part, out);
 }
 
 void cell_basis(int64_t n, int64_t nidx, const int32_t *idx, const int32_t *int2ext, const double *sc, double *zs,
@@ -133,11 +154,12 @@ void cell_basis(int64_t n, int64_t nidx, const int32_t *idx, const int32_t *int2
     if (nidx > 0) hipLaunchKernelGGL(k_cell_basis, dim3(grid(nidx)), dim3(TPB), 0, s, nidx, idx, int2ext, sc, zs, u);
 }
 
-void rows_spmv(int64_t n, const int32_t *rows, const int64_t *rowptr, const int32_t *col, const double *val,
-               const double *x, double *y, hipStream_t s) {
+void rows_sub_spmv(int64_t n, const int32_t *rows, const int64_t *wptr, const uint16_t *off, const int64_t *rowptr,
+                   const int32_t *col, const double *val, const double *x, double *y, hipStream_t s) {
     if (n <= 0) return;
     const int64_t nb = (n * RL + TPB - 1) / TPB;
-    hipLaunchKernelGGL(k_rows_spmv, dim3(unsigned(nb)), dim3(TPB), 0, s, n, rows, rowptr, col, val, x, y);
+    hipLaunchKernelGGL(k_rows_sub_spmv, dim3(unsigned(nb)), dim3(TPB), 0, s, n, rows, wptr, off, rowptr, col, val, x,
+                       y);
 }
 
 void fill_zero(int64_t n, double *y, hipStream_t s) {

@@ -70,16 +70,19 @@ void gauge_refresh(knp_ctx *c) {
         c->d_ns_w.alloc(size_t(N));
         c->d_ns_e.alloc(size_t(c->ns_ncell));
         c->d_ns_sum.alloc(size_t(c->ns_ncell));
+        c->d_ns_part.alloc(size_t(c->ns_ncell) * launch::CELL_SPLIT);
         launch::cell_basis(N, nidx, c->d_ns_idx.p, c->d_int2ext.p, c->d_sc.p, c->d_ns_zs.p, c->d_ns_u.p, s);
         launch::fill_zero(N, c->d_ns_w.p, s);
         c->ns_basis = true;
         c->ns_stale = true;
     }
     if (c->ns_stale) {
-        // W on the membrane rows; the rest of W stays 0 (A z_k vanishes there)
-        launch::rows_spmv(c->ns_nrows, c->d_ns_rows.p, c->d_rowptr_s.p, c->d_colidx.p, c->d_vals.p, c->d_ns_u.p,
-                          c->d_ns_w.p, s);
-        launch::cell_dot(c->ns_ncell, c->d_ns_ptr.p, c->d_ns_idx.p, c->d_ns_zs.p, c->d_ns_w.p, c->d_ns_e.p, s);
+        // W on the membrane rows, from their intracellular potential columns (u is 0 on the
+        // others); the rest of W stays 0 (A z_k vanishes there)
+        launch::rows_sub_spmv(c->ns_nrows, c->d_ns_rows.p, c->d_ns_wptr.p, c->d_ns_woff.p, c->d_rowptr_s.p,
+                              c->d_colidx.p, c->d_vals.p, c->d_ns_u.p, c->d_ns_w.p, s);
+        launch::cell_dot(c->ns_ncell, c->d_ns_ptr.p, c->d_ns_idx.p, c->d_ns_zs.p, c->d_ns_w.p, c->d_ns_part.p,
+                         c->d_ns_e.p, s);
         c->ns_stale = false;
     }
 }
@@ -125,11 +128,23 @@ void gauge_build(knp_ctx *c) {
     for (int k = 0; k < K; ++k) ptr[k + 1] += ptr[k];
     // the rows of membrane nodes (both regions): elsewhere every term of a row that
     // meets z_k is a divergence form, so (A z_k)_i is 0 up to rounding and W_i is kept 0
+    // and per such row the in-row positions of its intracellular potential columns (a
+    // storage row keeps its ABI row's entry order)
     std::vector<int32_t> rows;
+    std::vector<int64_t> wptr{0};
+    std::vector<uint16_t> woff;
     for (int64_t i = 0; i < N; ++i) {
         const int64_t e = c->int2ext[i];
         const int32_t v = e < 4 * Ni ? h.verts[0][e % Ni] : h.verts[1][(e - 4 * Ni) % Ne];
-        if (owner[i] >= 0 && h.gidx[v] >= 0) rows.push_back(int32_t(i));
+        if (owner[i] < 0 || h.gidx[v] < 0) continue;
+        rows.push_back(int32_t(i));
+        const int64_t a = h.rowptr[e], len = h.rowptr[e + 1] - a;
+        if (len > 65535) throw Error{KNP_E_ARG, "gauge 1: a membrane row holds more than 65535 entries"};
+        for (int64_t q = 0; q < len; ++q) {
+            const int64_t ce = h.colidx[a + q];
+            if (ce >= 3 * Ni && ce < 4 * Ni) woff.push_back(uint16_t(q));
+        }
+        wptr.push_back(int64_t(woff.size()));
     }
     std::vector<int32_t> idx(size_t(ptr[K]));
     {
@@ -149,9 +164,21 @@ void gauge_build(knp_ctx *c) {
     c->d_ns_rows.alloc(rows.size());
     c->d_ns_rows.upload(rows, s);
     c->ns_nrows = int64_t(rows.size());
+    c->d_ns_wptr.alloc(wptr.size());
+    c->d_ns_wptr.upload(wptr, s);
+    c->d_ns_woff.alloc(woff.size());
+    c->d_ns_woff.upload(woff, s);
     c->ns_ncell = K;
     c->ns_basis = false;
     c->ns_stale = true;
+}
+
+// y = b - (S A S) x, FP64: the product timed as the solver's true residual, then the
+// subtraction (folding it into the product's epilogue measured slower: b is read after
+// the row sums, its latency exposed)
+void residual(knp_ctx *c, bool transpose, const double *x, const double *b, double *y) {
+    apply_operator(c, transpose, x, y, KNP_TIMER_RESID_A);
+    launch::sub(c->hm.N, b, y, y, c->stream);
 }
 
 void apply_operator(knp_ctx *c, bool transpose, const double *x, double *y, int timer) {
@@ -211,10 +238,10 @@ knp_status krylov_solve(knp_ctx *c, bool transpose, const double *b, double *x, 
     // every exit below happens right after the residual of the current iterate is
     // recomputed, so that residual is the one reported
     while (true) {
-        apply_operator(c, transpose, yh, w, KNP_TIMER_RESID_A);
-        launch::sub(N, bh, w, w, s);
+        residual(c, transpose, yh, bh, w);
         if (gauge) {   // yh += sum_k c_k S^{-1} z_k, S r -= sum_k c_k S A z_k
-            launch::cell_dot(c->ns_ncell, c->d_ns_ptr.p, c->d_ns_idx.p, c->d_ns_zs.p, w, c->d_ns_sum.p, s);
+            launch::cell_dot(c->ns_ncell, c->d_ns_ptr.p, c->d_ns_idx.p, c->d_ns_zs.p, w, c->d_ns_part.p,
+                             c->d_ns_sum.p, s);
             launch::cell_correct(N, c->d_ns_owner.p, c->d_ns_w.p, c->d_ns_u.p, c->d_ns_sum.p, c->d_ns_e.p, w, yh, s);
         }
         const double beta = std::sqrt(dev_dot(c, w, w, N));
