@@ -213,7 +213,9 @@ knp_status knp_set_params(knp_ctx *ctx, const knp_params *params);
  *   f_out:  device [N] receives f_n (unscaled).
  * A_{n-1} stays in the context, stored as S A S with S = diag(P_0)^{-1/2} fixed
  * at the first call.  The first call also fixes P_0.  KNP_E_NUMERIC if u_prev
- * holds a NaN or Inf. */
+ * holds a NaN or Inf (checked before anything is written).  After that check the call
+ * only enqueues: f_out, gates and the stored system are ready in stream order, and
+ * the inputs must stay valid until the stream reaches the call's kernels. */
 knp_status knp_assemble_step(knp_ctx *ctx, double t_n, double dt, const double *u_prev,
                              double *gates, const double *theta, double *f_out);
 
@@ -230,7 +232,9 @@ knp_status knp_assemble_step(knp_ctx *ctx, double t_n, double dt, const double *
  *     fixes S and P_0), else KNP_E_STATE;
  *   - a mesh with more membrane vertices than the array holds is KNP_E_ARG;
  *   - calls that overlap on one device (several contexts or threads at once) share the
- *     array and race: serialise them. */
+ *     array and race: serialise them;
+ *   - it synchronises the stream before returning, so the array is free again on
+ *     return. */
 knp_status knp_assemble_step_noalloc(knp_ctx *ctx, double t_n, double dt, const double *u_prev,
                                      double *gates, const double *theta, double *f_out);
 
@@ -303,7 +307,8 @@ knp_status knp_step_vjp(knp_ctx *ctx, const double *u_prev, const double *u_n,
  * x0 = 2 u1 - u2 (device [N] each; u1 = u_{n-1}, u2 = u_{n-2}; x0 may alias either).
  * The paper starts each solve from the previous step (Sec. "Solver configurations");
  * the linear extrapolation in time is an alternative start that the caller may pass to
- * knp_gmres_solve as x.  Needs an uploaded mesh (N); blocks until done. */
+ * knp_gmres_solve as x.  Needs an uploaded mesh (N); enqueues one kernel and returns
+ * without synchronising (x0 is ready in stream order). */
 knp_status knp_extrapolate(knp_ctx *ctx, const double *u1, const double *u2, double *x0);
 
 /* Operator hooks for tests and measurement (device vectors of length N):

@@ -842,8 +842,9 @@ knp_status knp_assemble_step(knp_ctx *c, double t_n, double dt, const double *u_
             c->dt_first = dt;
         }
         hip_check(hipGetLastError(), "assembly launch");
-        hip_check(hipStreamSynchronize(s), "assembly");
-        c->tm.harvest();
+        // no synchronisation: the kernels run on after the return, in stream order with
+        // whatever the caller enqueues next; their timer events are read at the next
+        // synchronising call
         finish_assembly(c, t_n, dt, theta);
         return KNP_OK;
     });
@@ -1018,7 +1019,6 @@ knp_status knp_extrapolate(knp_ctx *c, const double *u1, const double *u2, doubl
         hip_check(hipSetDevice(c->device), "set device");
         launch::lincomb(c->hm.N, 2.0, u1, -1.0, u2, x0, c->stream);
         hip_check(hipGetLastError(), "extrapolate launch");
-        hip_check(hipStreamSynchronize(c->stream), "sync");
         return KNP_OK;
     });
 }

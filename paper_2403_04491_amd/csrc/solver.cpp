@@ -31,15 +31,6 @@ void ensure_pinned(knp_ctx *c, size_t count) {
     if (c->hbuf.n < count) c->hbuf.alloc(std::max<size_t>(count, 256));
 }
 
-double dev_dot(knp_ctx *c, const double *a, const double *b, int64_t n) {
-    // <a, b> via the multi-dot kernel with one vector (deterministic)
-    ensure_pinned(c, 1);
-    launch::multi_dot(n, a, n, 1, b, c->dscal.p, c->partial.p, c->nblk, c->stream);
-    hip_check(hipMemcpyAsync(c->hbuf.p, c->dscal.p, sizeof(double), hipMemcpyDeviceToHost, c->stream), "dot copy");
-    hip_check(hipStreamSynchronize(c->stream), "dot sync");
-    return c->hbuf.p[0];
-}
-
 void ensure_workspace(knp_ctx *c, int m, bool z32) {
     const int64_t N = c->hm.N;
     if (c->m_alloc >= m && c->z32 == z32) return;
@@ -210,15 +201,11 @@ knp_status krylov_solve(knp_ctx *c, bool transpose, const double *b, double *x, 
     // into the solver's order and scaling: bh = S b, yh = S^{-1} x
     launch::to_internal(N, c->d_int2ext.p, b, c->d_sc.p, bh, 0, s);
     launch::to_internal(N, c->d_int2ext.p, x, c->d_sc.p, yh, 1, s);
-    const double bnorm = std::sqrt(dev_dot(c, bh, bh, N));
+    // ||S b||^2 goes to dscal[1] and reaches the host with the first residual's norm
+    // (one synchronisation for both; the Arnoldi process overwrites the slot later)
+    launch::multi_dot(N, bh, N, 1, bh, c->dscal.p + 1, c->partial.p, c->nblk, s);
+    double bnorm = -1.0;   // not yet read
     knp_solve_info inf{};
-    if (!std::isfinite(bnorm)) throw Error{KNP_E_NUMERIC, "NaN or Inf in the right-hand side"};
-    if (bnorm == 0.0) {
-        hip_check(hipMemsetAsync(x, 0, size_t(N) * sizeof(double), s), "zero x");
-        hip_check(hipStreamSynchronize(s), "sync");
-        if (info) *info = inf;
-        return KNP_OK;
-    }
     const bool gauge = c->gauge == 1 && !transpose;
     if (gauge) gauge_refresh(c);
     std::vector<double> H(size_t(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
@@ -244,7 +231,23 @@ knp_status krylov_solve(knp_ctx *c, bool transpose, const double *b, double *x, 
                              c->d_ns_sum.p, s);
             launch::cell_correct(N, c->d_ns_owner.p, c->d_ns_w.p, c->d_ns_u.p, c->d_ns_sum.p, c->d_ns_e.p, w, yh, s);
         }
-        const double beta = std::sqrt(dev_dot(c, w, w, N));
+        launch::multi_dot(N, w, N, 1, w, c->dscal.p, c->partial.p, c->nblk, s);
+        const int nread = bnorm < 0.0 ? 2 : 1;
+        hip_check(hipMemcpyAsync(c->hbuf.p, c->dscal.p, sizeof(double) * nread, hipMemcpyDeviceToHost, s),
+                  "norm copy");
+        hip_check(hipStreamSynchronize(s), "norm sync");
+        if (bnorm < 0.0) {
+            bnorm = std::sqrt(c->hbuf.p[1]);
+            if (!std::isfinite(bnorm)) throw Error{KNP_E_NUMERIC, "NaN or Inf in the right-hand side"};
+            if (bnorm == 0.0) {
+                hip_check(hipMemsetAsync(x, 0, size_t(N) * sizeof(double), s), "zero x");
+                hip_check(hipStreamSynchronize(s), "sync");
+                c->tm.harvest();
+                if (info) *info = inf;
+                return KNP_OK;
+            }
+        }
+        const double beta = std::sqrt(c->hbuf.p[0]);
         if (!std::isfinite(beta)) throw Error{KNP_E_NUMERIC, "NaN or Inf in the residual"};
         est = beta / bnorm;
         true_rel = est;
@@ -334,7 +337,9 @@ knp_status krylov_solve(knp_ctx *c, bool transpose, const double *b, double *x, 
             for (int k = i + 1; k < jend; ++k) t -= Hc(i, k) * y[k];
             y[i] = Hc(i, i) != 0.0 ? t / Hc(i, i) : 0.0;
         }
-        // (through pinned memory; the stream is synchronised before it is reused)
+        // through pinned memory: the host writes it next only after the next cycle's
+        // synchronisations, and the device-to-host copies into it are stream-ordered
+        // after this copy
         std::memcpy(c->hbuf.p, y.data(), sizeof(double) * jend);
         hip_check(hipMemcpyAsync(c->dscal.p, c->hbuf.p, sizeof(double) * jend, hipMemcpyHostToDevice, s), "y");
         if (!use_amg)
@@ -343,7 +348,6 @@ knp_status krylov_solve(knp_ctx *c, bool transpose, const double *b, double *x, 
             launch::multi_axpy<float>(N, c->Z32.p, N, jend, c->dscal.p, yh, s);
         else
             launch::multi_axpy<double>(N, c->Z64.p, N, jend, c->dscal.p, yh, s);
-        hip_check(hipStreamSynchronize(s), "update sync");
         inf.rel_res_est = est;
     }
     inf.rel_res = true_rel;
