@@ -130,7 +130,10 @@ typedef struct {
 typedef struct {
     int32_t its;            /* iterations performed                               */
     int32_t restarts;
-    double rel_res;         /* recomputed ||S(b - A x)|| / ||S b|| at return      */
+    double rel_res;         /* ||S(b - A x)|| / ||S b|| of the returned x: from a
+                               product with A, or (rtol >= 1e-10, the last cycle's
+                               estimate within rtol) the Arnoldi relation's
+                               V (beta e_1 - H y), equal up to rounding            */
     double rel_res_est;     /* the recurrence's estimate at the last iteration    */
 } knp_solve_info;
 

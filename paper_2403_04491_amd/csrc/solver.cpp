@@ -43,7 +43,7 @@ void ensure_workspace(knp_ctx *c, int m, bool z32) {
     else
         c->Z64.alloc(size_t(m) * N);
     c->dscal.release();
-    c->dscal.alloc(size_t(m) + 64);
+    c->dscal.alloc(2 * size_t(m) + 64);
     ensure_pinned(c, 2 * size_t(m) + 8);
     c->m_alloc = m;
     c->z32 = z32;
@@ -208,8 +208,20 @@ knp_status krylov_solve(knp_ctx *c, bool transpose, const double *b, double *x, 
     knp_solve_info inf{};
     const bool gauge = c->gauge == 1 && !transpose;
     if (gauge) gauge_refresh(c);
-    std::vector<double> H(size_t(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+    std::vector<double> H(size_t(m + 1) * m), H0(size_t(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
     auto Hc = [&](int i, int j) -> double & { return H[size_t(j) * (m + 1) + i]; };
+    auto H0c = [&](int i, int j) -> double & { return H0[size_t(j) * (m + 1) + i]; };   // before the rotations
+    // At rtol >= UPDATED_MIN_RTOL, a cycle whose recurrence estimate meets rtol is tested on
+    // the residual of its updated iterate formed from the Arnoldi relation,
+    // r0 - (S A S) Z y = V (beta e_1 - H y), instead of a product with the operator: the two
+    // differ by rounding in that relation (of the order of the unit roundoff times the
+    // sizes of the products (S A S) z_j y_j), far below such tolerances.  Below it, and
+    // whenever that residual misses rtol, the residual comes from a product.
+    constexpr double UPDATED_MIN_RTOL = 1e-10;
+    bool try_updated = false;
+    int upd_j = 0;          // the cycle's last basis index: c = [c_0, ..., c_upd_j]
+    double upd_c0 = 0.0;    // c_0 (host); c_1 ... in dscal[upd_j + 1 ...]
+    std::vector<double> coef(size_t(m) + 1);
     int its = 0, restarts = 0;
     double est = 1.0;
     bool converged = false;
@@ -221,11 +233,18 @@ knp_status krylov_solve(knp_ctx *c, bool transpose, const double *b, double *x, 
     int stall = 0;
     bool cycle_est_converged = false;
     double window_beta = 0.0;
-    double true_rel = 1.0;   // recomputed residual of the current iterate
-    // every exit below happens right after the residual of the current iterate is
-    // recomputed, so that residual is the one reported
+    double true_rel = 1.0;   // residual of the current iterate
+    // every exit below happens right after the residual of the current iterate is formed
+    // (by a product, or from the Arnoldi relation), so that residual is the one reported
     while (true) {
-        residual(c, transpose, yh, bh, w);
+        const bool updated = try_updated;
+        try_updated = false;
+        if (updated) {   // w = V c = c_0 v_0 + sum_{i >= 1} c_i v_i
+            launch::axpby(N, upd_c0, c->V.p, 0.0, w, s);
+            launch::multi_axpy<double>(N, c->V.p + N, N, upd_j, c->dscal.p + upd_j + 1, w, s);
+        } else {
+            residual(c, transpose, yh, bh, w);
+        }
         if (gauge) {   // yh += sum_k c_k S^{-1} z_k, S r -= sum_k c_k S A z_k
             launch::cell_dot(c->ns_ncell, c->d_ns_ptr.p, c->d_ns_idx.p, c->d_ns_zs.p, w, c->d_ns_part.p,
                              c->d_ns_sum.p, s);
@@ -255,6 +274,7 @@ knp_status krylov_solve(knp_ctx *c, bool transpose, const double *b, double *x, 
             converged = true;
             break;
         }
+        if (updated) continue;   // missed rtol: the residual from a product decides
         if (its >= o.max_it) break;
         if (restarts > 0 && cycle_est_converged && beta > 0.5 * window_beta) {
             if (++stall >= STALL_WINDOW) break;
@@ -309,8 +329,8 @@ knp_status krylov_solve(knp_ctx *c, bool transpose, const double *b, double *x, 
             hip_check(hipStreamSynchronize(s), "gs sync");
             const double hn = std::sqrt(hp[m + 1]);
             if (!std::isfinite(hn)) throw Error{KNP_E_NUMERIC, "NaN or Inf in the Arnoldi process"};
-            for (int i = 0; i <= j; ++i) Hc(i, j) = o.reorth ? hp[m + 2 + i] + hp[i] : hp[i];
-            Hc(j + 1, j) = hn;
+            for (int i = 0; i <= j; ++i) Hc(i, j) = H0c(i, j) = o.reorth ? hp[m + 2 + i] + hp[i] : hp[i];
+            Hc(j + 1, j) = H0c(j + 1, j) = hn;
             if (hn > 0.0) launch::scale_by_inv_norm(N, wj, dh + m + 1, wj, s);
             // Givens rotations
             for (int i = 0; i < j; ++i) {
@@ -337,11 +357,26 @@ knp_status krylov_solve(knp_ctx *c, bool transpose, const double *b, double *x, 
             for (int k = i + 1; k < jend; ++k) t -= Hc(i, k) * y[k];
             y[i] = Hc(i, i) != 0.0 ? t / Hc(i, i) : 0.0;
         }
+        // the updated iterate's residual coefficients, c = beta e_1 - H y (H as the Arnoldi
+        // process built it, before the rotations)
+        int ncopy = jend;
+        if (cycle_est_converged && o.rtol >= UPDATED_MIN_RTOL) {
+            for (int i = 0; i <= jend; ++i) {
+                double t = i == 0 ? beta : 0.0;
+                for (int k = std::max(0, i - 1); k < jend; ++k) t -= H0c(i, k) * y[k];
+                coef[i] = t;
+            }
+            try_updated = true;
+            upd_j = jend;
+            upd_c0 = coef[0];
+            ncopy = 2 * jend + 1;   // dscal[0, jend): y; dscal[jend, 2 jend + 1): c
+        }
         // through pinned memory: the host writes it next only after the next cycle's
         // synchronisations, and the device-to-host copies into it are stream-ordered
         // after this copy
         std::memcpy(c->hbuf.p, y.data(), sizeof(double) * jend);
-        hip_check(hipMemcpyAsync(c->dscal.p, c->hbuf.p, sizeof(double) * jend, hipMemcpyHostToDevice, s), "y");
+        if (try_updated) std::memcpy(c->hbuf.p + jend, coef.data(), sizeof(double) * (jend + 1));
+        hip_check(hipMemcpyAsync(c->dscal.p, c->hbuf.p, sizeof(double) * ncopy, hipMemcpyHostToDevice, s), "y");
         if (!use_amg)
             launch::multi_axpy<double>(N, c->V.p, N, jend, c->dscal.p, yh, s);
         else if (z32)
@@ -351,7 +386,7 @@ knp_status krylov_solve(knp_ctx *c, bool transpose, const double *b, double *x, 
         inf.rel_res_est = est;
     }
     inf.rel_res = true_rel;
-    if (converged) inf.rel_res_est = est;
+    if (its == 0) inf.rel_res_est = true_rel;   // no iteration: the estimate is the residual
     inf.its = its;
     inf.restarts = restarts;
     launch::to_external(N, c->d_int2ext.p, yh, c->d_sc.p, x, 0, s);   // x = S yh
