@@ -561,6 +561,7 @@ void cell_dot(int ncell, const int64_t *ptr, const int32_t *idx, const double *z
 void cell_basis(int64_t n, int64_t nidx, const int32_t *idx, const int32_t *int2ext, const double *sc, double *zs,
                 double *u, hipStream_t s);
 // c_k = sum[k] / E[k]; r[i] -= c_owner(i) W[i], y[i] += c_owner(i) u[i] where owner(i) >= 0
+// (r or y null: that update skipped)
 void cell_correct(int64_t n, const int32_t *owner, const double *W, const double *u, const double *sum,
                   const double *E, double *r, double *y, hipStream_t s);
 // y[rows[t]] = sum of val[q] x[col[q]] over the listed entries q = rowptr[rows[t]] + off[e],

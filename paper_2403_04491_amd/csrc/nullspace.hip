@@ -78,7 +78,8 @@ __global__ void k_fill(int64_t n, double *__restrict__ y) {
 }
 
 // With c_k = sum[k] / E[k] (0 if E[k] is 0 or not finite): r[i] -= c_k W[i] and
-// y[i] += c_k u[i] for every storage DOF i whose rows couple to cell k (owner k >= 0)
+// y[i] += c_k u[i] for every storage DOF i whose rows couple to cell k (owner k >= 0);
+// a null r or y skips that update
 __global__ void k_cell_correct(int64_t n, const int32_t *__restrict__ owner, const double *__restrict__ W,
                                const double *__restrict__ u, const double *__restrict__ sum,
                                const double *__restrict__ E, double *__restrict__ r, double *__restrict__ y) {
@@ -87,8 +88,8 @@ __global__ void k_cell_correct(int64_t n, const int32_t *__restrict__ owner, con
         if (k < 0) continue;
         const double e = E[k];
         const double c = (e != 0.0 && isfinite(e)) ? sum[k] / e : 0.0;
-        r[i] -= c * W[i];
-        y[i] += c * u[i];
+        if (r) r[i] -= c * W[i];
+        if (y) y[i] += c * u[i];
     }
 }
 

@@ -214,10 +214,13 @@ knp_status krylov_solve(knp_ctx *c, bool transpose, const double *b, double *x, 
     // At rtol >= UPDATED_MIN_RTOL, a cycle whose recurrence estimate meets rtol is tested on
     // the residual of its updated iterate formed from the Arnoldi relation,
     // r0 - (S A S) Z y = V (beta e_1 - H y), instead of a product with the operator: the two
-    // differ by rounding in that relation (of the order of the unit roundoff times the
-    // sizes of the products (S A S) z_j y_j), far below such tolerances.  Below it, and
-    // whenever that residual misses rtol, the residual comes from a product.
+    // differ by rounding in that relation, of the order of the unit roundoff times
+    // G = sqrt(j + 1) sum_k |y_k| ||H e_k|| (the sizes of the products (S A S) z_k y_k it
+    // sums), and the form is used only while UPDATED_EPS G stays below a hundredth of the
+    // tolerance.  Below UPDATED_MIN_RTOL, and whenever that residual misses rtol, the
+    // residual comes from a product, and the iterate is then exactly as without the test.
     constexpr double UPDATED_MIN_RTOL = 1e-10;
+    constexpr double UPDATED_EPS = 1e-12;
     bool try_updated = false;
     int upd_j = 0;          // the cycle's last basis index: c = [c_0, ..., c_upd_j]
     double upd_c0 = 0.0;    // c_0 (host); c_1 ... in dscal[upd_j + 1 ...]
@@ -245,10 +248,12 @@ knp_status krylov_solve(knp_ctx *c, bool transpose, const double *b, double *x, 
         } else {
             residual(c, transpose, yh, bh, w);
         }
-        if (gauge) {   // yh += sum_k c_k S^{-1} z_k, S r -= sum_k c_k S A z_k
+        if (gauge) {   // yh += sum_k c_k S^{-1} z_k, S r -= sum_k c_k S A z_k (yh only once
+                       // an updated residual has passed the test)
             launch::cell_dot(c->ns_ncell, c->d_ns_ptr.p, c->d_ns_idx.p, c->d_ns_zs.p, w, c->d_ns_part.p,
                              c->d_ns_sum.p, s);
-            launch::cell_correct(N, c->d_ns_owner.p, c->d_ns_w.p, c->d_ns_u.p, c->d_ns_sum.p, c->d_ns_e.p, w, yh, s);
+            launch::cell_correct(N, c->d_ns_owner.p, c->d_ns_w.p, c->d_ns_u.p, c->d_ns_sum.p, c->d_ns_e.p, w,
+                                 updated ? nullptr : yh, s);
         }
         launch::multi_dot(N, w, N, 1, w, c->dscal.p, c->partial.p, c->nblk, s);
         const int nread = bnorm < 0.0 ? 2 : 1;
@@ -271,6 +276,9 @@ knp_status krylov_solve(knp_ctx *c, bool transpose, const double *b, double *x, 
         est = beta / bnorm;
         true_rel = est;
         if (est <= o.rtol) {
+            if (updated && gauge)
+                launch::cell_correct(N, c->d_ns_owner.p, c->d_ns_w.p, c->d_ns_u.p, c->d_ns_sum.p, c->d_ns_e.p,
+                                     nullptr, yh, s);
             converged = true;
             break;
         }
@@ -360,7 +368,14 @@ knp_status krylov_solve(knp_ctx *c, bool transpose, const double *b, double *x, 
         // the updated iterate's residual coefficients, c = beta e_1 - H y (H as the Arnoldi
         // process built it, before the rotations)
         int ncopy = jend;
-        if (cycle_est_converged && o.rtol >= UPDATED_MIN_RTOL) {
+        double G = 0.0;
+        for (int k = 0; k < jend && cycle_est_converged; ++k) {
+            double cn = 0.0;
+            for (int i = 0; i <= k + 1; ++i) cn += H0c(i, k) * H0c(i, k);
+            G += std::fabs(y[k]) * std::sqrt(cn);
+        }
+        G *= std::sqrt(double(jend + 1));
+        if (cycle_est_converged && o.rtol >= UPDATED_MIN_RTOL && UPDATED_EPS * (G + beta) <= 0.01 * o.rtol * bnorm) {
             for (int i = 0; i <= jend; ++i) {
                 double t = i == 0 ? beta : 0.0;
                 for (int k = std::max(0, i - 1); k < jend; ++k) t -= H0c(i, k) * y[k];
