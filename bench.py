@@ -181,7 +181,7 @@ def measured_traffic(kernel, precision, n):
     return None if k is None else k.get("bytes_per_launch")
 
 
-def survey_unit_bytes(kernel, info, precision):
+def csr_model_bytes(kernel, info, precision):
     """Bytes of one launch in the CSR unit of the byte model the path was planned on
     (SpMV(A): 12 per nonzero + 24 per row; SpMV(P_0) on the finest level: 12 or 8 per
     nonzero + 24 or 16 per row for FP64 or FP32 levels), which credits any compression
@@ -215,7 +215,7 @@ def roofline_of(timers, precision=None, info=None):
            "frac_layout": round(achieved / PEAK_HBM_GBS, 4),
            "traffic_ratio": None if traffic is None else round(traffic / per_launch_bytes, 3)}
     if info is not None and precision is not None:
-        sb = survey_unit_bytes(best, info, precision)
+        sb = csr_model_bytes(best, info, precision)
         out["bytes_survey_unit"] = sb
         out["frac_survey"] = round(sb / avg_s / 1e9 / PEAK_HBM_GBS, 4)
     return best, out
